@@ -1,0 +1,60 @@
+"""Shape checks of the seeded input generators (scaled-down workloads)."""
+import numpy as np
+
+import synth
+
+
+def _well_formed(g, smin, smax):
+    sizes = g.sizes()
+    assert g.e_off[0] == 0 and g.e_off[-1] == g.kappa and np.all(sizes >= 0)
+    assert sizes.min() >= smin and sizes.max() <= smax
+    assert g.e_pins.min() >= 0 and g.e_pins.max() < g.n
+    eid = np.repeat(np.arange(g.m), sizes)
+    key = eid.astype(np.int64) * g.n + g.e_pins
+    assert np.unique(key).size == g.kappa                 # pins distinct within an edge
+    # the vertex side is the exact transpose of the edge side
+    vid = np.repeat(np.arange(g.n), g.degrees())
+    key_v = g.v_edges.astype(np.int64) * g.n + vid
+    assert np.array_equal(np.sort(key), np.sort(key_v))
+    assert g.v_off[-1] == g.kappa
+
+
+def test_plain_config_shape():
+    g = synth.config_plain()
+    assert (g.n, g.m) == (10_000, 20_000)
+    _well_formed(g, 2, 8)
+    assert g.w.min() >= 1 and g.w.max() <= 1000
+    again = synth.config_plain()
+    assert np.array_equal(g.e_pins, again.e_pins) and np.array_equal(g.w, again.w)
+
+
+def test_power_law_shape_scaled():
+    g = synth.config_power_law(seed=5, n=40_000, m=100_000)
+    _well_formed(g, 2, 64)
+    deg = g.degrees()
+    assert deg.max() > 20 * deg.mean()            # skewed degrees with hubs
+    assert (deg == 0).mean() > 0.1                # many unused vertices
+    assert g.w.min() >= 1 and g.w.max() <= 2 ** 20
+    assert 5.0 < g.sizes().mean() < 7.0           # Zipf(2) on {2..64}: mean about 5.95
+
+
+def test_hub_shape_scaled():
+    g = synth.config_hub_stress(seed=6, n=20_000, m=80_000)
+    _well_formed(g, 2, 16)
+    assert g.degrees()[g.hub] == 20_000
+    assert np.all(g.w == 1)
+
+
+def test_batch_layout():
+    b = synth.config_batched(seed=8, count=12, n_lo=50, n_hi=500)
+    assert b.count == 12 and np.all(b.m == 2 * b.n)
+    for i in range(b.count):
+        g = b.instance(i)
+        _well_formed(g, 2, 12)
+        assert g.e_off.shape[0] == g.m + 1 and g.v_off.shape[0] == g.n + 1
+
+
+def test_poisson_arrivals():
+    t = synth.gen.poisson_arrivals(1, 2000.0, 5.0)
+    assert np.all(np.diff(t) > 0) and t[-1] < 5.0
+    assert abs(t.size - 10_000) < 500
