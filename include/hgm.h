@@ -1,0 +1,133 @@
+/*
+ * hgm: weighted hypergraph matching by iterated local maxima on AMD MI355X.
+ *
+ * The method (paper: "Efficient Parallel Algorithms for Hypergraph Matching",
+ * Section 4.1 Sequential Algorithm, Algorithms 1 and 2) works in rounds.
+ * Every live hyperedge e carries a key; every vertex takes the largest key
+ * over its live incident edges; an edge whose key is that largest value at
+ * all of its pins joins the matching; every live edge that touches a pin of a
+ * newly matched edge is retired (soft delete).  Rounds repeat until no live
+ * edge remains.
+ *
+ * Key.  The paper perturbs the weights with random noise (Section 5.1, noise
+ * in (0,1) for integer weights, extra noise for ties).  Here every edge gets
+ * one fixed key for all rounds, compared as the tuple
+ *     (w(e), H(seed, e), e)      larger is better,
+ * where H(seed, e) = MurmurHash3_x86_32 of e's four little-endian bytes with
+ * the given seed.  H is a bijection of e for a fixed seed, so keys are
+ * distinct and the id never decides.  With a fixed strict order the local-max
+ * rounds select exactly the matching that sequential greedy selects in that
+ * order, so there is one correct output per (instance, seed).
+ *
+ * Conventions for every entry point:
+ *  - All array pointers inside hgm_csr, the output bitmap and the workspace
+ *    are DEVICE pointers owned by the caller; the library allocates nothing.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *    it; hgm_match synchronises that stream at least once every
+ *    opts->rounds_per_sync rounds to test for termination, and returns when
+ *    the matching is complete in device memory.
+ *  - Return value: HGM_OK (0) or a negative HGM_E_* code; no exception or
+ *    abort crosses this interface.  hgm_strerror() describes a code.
+ *  - Calls that share a workspace must not overlap.
+ */
+#ifndef HGM_H
+#define HGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HGM_OK 0
+#define HGM_E_ARG (-1)         /* NULL pointer with a non-zero size, negative size, bad option */
+#define HGM_E_CSR (-2)         /* malformed input detected by opts->validate */
+#define HGM_E_SIZE (-3)        /* kappa >= 2^31, or workspace too small */
+#define HGM_E_ROUND_LIMIT (-4) /* opts->max_rounds rounds ran and live edges remain */
+#define HGM_E_HIP (-5)         /* a HIP runtime call failed */
+
+/* Round variants.  Both compute the same result (Algorithm 1 vs Algorithm 2
+ * of the paper differ in how the per-vertex maximum is formed). */
+#define HGM_VARIANT_AUTO 0 /* library choice per round */
+#define HGM_VARIANT_CRCW 1 /* edge-centric: 64-bit atomic max of the key at each pin */
+#define HGM_VARIANT_CREW 2 /* vertex-centric: segmented max over each vertex's edge list */
+
+/* Hypergraph in the dual compressed form of the paper (Section 5.1):
+ *   e_off   int32[m+1]  e_off[0] = 0, non-decreasing, e_off[m] = kappa
+ *   e_pins  int32[kappa] pins of edge e are e_pins[e_off[e] .. e_off[e+1]),
+ *                        distinct, each in [0, n)
+ *   v_off   int32[n+1]  v_off[0] = 0, non-decreasing, v_off[n] = kappa
+ *   v_edges int32[kappa] edges containing v are v_edges[v_off[v] .. v_off[v+1]);
+ *                        the exact transpose of e_pins (any order inside a list)
+ *   w       uint32[m]   edge weights (0 allowed)
+ * Empty edges (size 0) are allowed and are matched (they conflict with
+ * nothing); degree-0 vertices are allowed.  v_off/v_edges are read only by
+ * the CREW variant and by validation; they may be NULL when opts->variant is
+ * HGM_VARIANT_CRCW and validation is off. */
+typedef struct hgm_csr {
+    int32_t n, m;
+    int64_t kappa;
+    const int32_t *e_off;
+    const int32_t *e_pins;
+    const int32_t *v_off;
+    const int32_t *v_edges;
+    const uint32_t *w;
+} hgm_csr;
+
+/* Options; a NULL pointer means all defaults (the value 0 of each field). */
+typedef struct hgm_opts {
+    int32_t variant;         /* HGM_VARIANT_*; 0 = AUTO */
+    int32_t hub_threshold;   /* CREW: vertices of larger degree are split over
+                                several workgroups; 0 = library default */
+    int32_t rounds_per_sync; /* rounds enqueued between host termination checks;
+                                0 = library default */
+    int32_t validate;        /* 1 = check the input first (extra O(kappa d) work
+                                and one synchronisation); HGM_E_CSR on failure */
+    int32_t max_rounds;      /* > 0: fail with HGM_E_ROUND_LIMIT if live edges
+                                remain after this many rounds; 0 = no limit */
+} hgm_opts;
+
+/* Optional statistics (host memory).  The arrays may be NULL; when given they
+ * hold `cap` entries and receive, for round r < cap: the number of live edges
+ * at the start of round r, the sum of their sizes (live pin incidences), and
+ * the number of edges matched in round r.  `rounds` is the number of rounds
+ * run, `matched` = |M|, `weight` = w(M) (64-bit sum). */
+typedef struct hgm_stats {
+    int32_t rounds;
+    int64_t matched;
+    uint64_t weight;
+    int64_t *live_edges;
+    int64_t *live_pins;
+    int64_t *matched_per_round;
+    int32_t cap;
+} hgm_stats;
+
+/* Bytes of device workspace hgm_match needs for this instance and options.
+ * Returns 0 when g is NULL or its sizes are invalid. */
+size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts);
+
+/* Match one hypergraph.
+ *   g             input (device arrays, see hgm_csr)
+ *   seed          seed of the priority hash H
+ *   matched_bits  device uint32[ceil(m/32)], written: bit (e % 32) of word
+ *                 e / 32 is 1 iff edge e is in the matching (LSB first)
+ *   workspace     device memory of at least hgm_workspace_size() bytes,
+ *                 256-byte aligned; contents on entry are ignored
+ *   opts, stream  see above; stats may be NULL
+ * Paper: Algorithm 1 (CRCW) and Algorithm 2 (CREW), with the soft delete of
+ * Section 4.1 realised as a compacted list of live edges. */
+int hgm_match(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits, void *workspace,
+              size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats);
+
+/* Short English description of an HGM_* code (static storage). */
+const char *hgm_strerror(int code);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int hgm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGM_H */

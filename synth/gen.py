@@ -51,9 +51,9 @@ def transpose(n: int, e_off: np.ndarray, e_pins: np.ndarray):
     """Vertex side of the dual form: v_off[n+1], v_edges[kappa] (stable)."""
     m = e_off.shape[0] - 1
     sizes = np.diff(e_off.astype(np.int64))
-    eid = np.repeat(np.arange(m, dtype=np.int32), sizes)
-    order = np.argsort(e_pins, kind="stable")
-    v_edges = eid[order].astype(np.int32)
+    eid = np.repeat(np.arange(m, dtype=np.int64), sizes)
+    key = np.sort(e_pins.astype(np.int64) * (1 << 32) + eid)   # by vertex, then edge id
+    v_edges = (key & 0xFFFFFFFF).astype(np.int32)
     deg = np.bincount(e_pins, minlength=n).astype(np.int64) if e_pins.size else np.zeros(n, np.int64)
     v_off = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(deg, out=v_off[1:])
@@ -99,8 +99,8 @@ def _draw_distinct(rng, sizes, off, sample):
 
 def _sort_within_edges(m, sizes, pins):
     eid = np.repeat(np.arange(m, dtype=np.int64), sizes)
-    order = np.lexsort((pins, eid))
-    return pins[order]
+    key = np.sort(eid * (1 << 32) + pins.astype(np.int64))
+    return key & 0xFFFFFFFF
 
 
 def from_edge_lists(n: int, edges, w) -> Hypergraph:

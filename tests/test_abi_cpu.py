@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2602_22976_amd as hgm
+from paper_2602_22976_amd import build as hb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hb.LIB):
+        hb.build(force=True)
+    return hgm.load()
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(hgm_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "hgm_match" in names and "hgm_workspace_size" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(hgm.EXPORTED) <= set(names)
+
+
+def test_strerror_and_version(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(hgm.hgm_strerror(code)) > 5
+    assert "unknown" in hgm.hgm_strerror(-99)
+    assert hgm.hgm_version() >= 100
+
+
+def _csr(n, m, kappa):
+    c = hgm.HgmCsr()
+    c.n, c.m, c.kappa = n, m, kappa
+    fake = 0x1000
+    c.e_off = c.e_pins = c.v_off = c.v_edges = c.w = fake
+    return c
+
+
+def test_workspace_size_layout(lib):
+    small = hgm.hgm_workspace_size(_csr(10, 20, 100))
+    big = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000))
+    assert 0 < small < big
+    # keys 8m, two max buffers 16n, done n, two lists 8m at least
+    assert big >= 16 * 5_000_000 + 17 * 2_000_000
+    crew = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts("crew"))
+    assert crew > big
+    val = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000),
+                                 hgm.make_opts(validate=True))
+    assert val >= big + 30_000_000 // 8 - 4096
+    assert hgm.hgm_workspace_size(_csr(-1, 5, 5)) == 0
+    assert hgm.hgm_workspace_size(_csr(5, 5, 2 ** 31)) == 0
+    assert hgm.hgm_workspace_size(_csr(5, 5, 5), hgm.make_opts(variant=7)) == 0
+
+
+def test_match_rejects_bad_arguments_without_gpu(lib):
+    ws = 0x100000
+    bits = 0x2000
+    # negative sizes, huge kappa, bad option, misaligned or short workspace
+    assert hgm.hgm_match(_csr(-1, 5, 5), 1, bits, ws, 1 << 30) == hgm.HGM_E_ARG
+    assert hgm.hgm_match(_csr(5, 5, 2 ** 31), 1, bits, ws, 1 << 30) == hgm.HGM_E_SIZE
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30,
+                         hgm.make_opts(variant=9)) == hgm.HGM_E_ARG
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 16) == hgm.HGM_E_SIZE
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws + 8, 1 << 30) == hgm.HGM_E_ARG
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, 0, ws, 1 << 30) == hgm.HGM_E_ARG
+    c = _csr(5, 5, 5)
+    c.e_pins = None
+    assert hgm.hgm_match(c, 1, bits, ws, 1 << 30) == hgm.HGM_E_ARG
+    c = _csr(5, 5, 5)
+    c.v_edges = None
+    assert hgm.hgm_match(c, 1, bits, ws, 1 << 30, hgm.make_opts("crew")) == hgm.HGM_E_ARG
+    assert lib.hgm_match(None, 1, None, None, 0, None, None, None) == hgm.HGM_E_ARG
+    st = hgm.HgmStats()
+    st.cap = 4
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, None, 0, st) == hgm.HGM_E_ARG
+    o = hgm.make_opts(rounds_per_sync=1000)
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
+
+
+def test_product_package_does_not_use_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2602_22976_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "oracle_" not in text, fn
