@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark of one hgm_match step on one MI355X.
+
+A step is one whole matching of the workload: key construction, every round
+(maximum, test, retire + compaction) until no live edge remains, and the
+host's termination checks.  Inputs are resident in HBM before timing starts.
+
+Printed (one JSON line):
+  value        live pin incidences processed per second, sum over rounds of
+               kappa_r divided by the step time (the per-round incidence
+               throughput of the method, all overheads included)
+  roofline     the dominant kernel's algorithmic bytes / its HIP-event time,
+               against the 8 TB/s HBM peak; `traffic` from the committed
+               rocprofv3 PMC summary when it matches the kernel source
+  cpu_baseline the oracle's round simulator on the host (one core), same unit
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pin-incidences/s per round + hypergraphs/s batched vs plain; p50/p99 latency"
+
+WORKLOADS = {
+    "power-law": ("config_power_law", "large power-law: n=2,000,000, m=5,000,000, |e|~Zipf(2.0) "
+                  "on [2,64], vertex popularity Zipf(1.1), w log-uniform [1,2^20], seed 1"),
+    "hub": ("config_hub_stress", "hub-stress: n=1,000,000, m=4,000,000, |e|~U[2,16], one hub "
+            "in 25% of edges, all w=1, seed 1"),
+    "plain": ("config_plain", "plain: n=10,000, m=20,000, |e|~U[2,8], w~U[1,1000], seed 1"),
+}
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for fn in ("kernels.hip", "api.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_22976_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(stats, variant_rounds, n):
+    """Bytes each kernel class must move, from the per-round counts.
+
+    Units per round r: E = live edges, K = their pins, M / P = matched edges
+    and their pins, E' / K' = survivors into round r+1.  Counts each array
+    element the step needs once (re-reads from cache are not algorithmic):
+      scatter (round 0): 12 B/edge (offset 4, key 8) + 12 B/pin (pin 4, atomic 8)
+      test:   per edge id 4 (not in round 0) + offsets 8 + key 8, per pin
+              pin 4 + best 8 (+ 8 clearing next round's buffer in CRCW),
+              per matched edge 4 (bitmap) and per matched pin 1 (done)
+      retire: per edge id 4 (not in round 0) + offsets 8, per pin pin 4 +
+              done 1, per survivor id write 4 (+ key 8 and 8 per surviving
+              pin for the fused CRCW scatter; CREW: 8 per dead edge key)
+      vertex max (CREW): per vertex done 1 + offsets 4 + best 8, per pin of
+              a vertex still open v_edges 4 + key 8 (counted over all pins)
+    """
+    E = list(stats["live_edges"]) + [0]
+    K = list(stats["live_pins"]) + [0]
+    M = stats["matched_per_round"]
+    P = stats["matched_pins"]
+    R = stats["rounds"]
+    out = {"scatter": 0.0, "test": 0.0, "retire": 0.0, "vertex_max": 0.0}
+    for r in range(R):
+        crew_r = variant_rounds(r)
+        crew_next = variant_rounds(r + 1)
+        idb = 0 if r == 0 else 4
+        if r == 0 and not crew_r:
+            out["scatter"] += 12 * E[0] + 12 * K[0]
+        if crew_r:
+            out["vertex_max"] += 13 * n + 12 * K[0]
+        out["test"] += (idb + 16) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
+        ret = (idb + 8) * E[r] + 5 * K[r] + 4 * E[r + 1]
+        if crew_next:
+            ret += 8 * (E[r] - E[r + 1])
+        else:
+            ret += 8 * E[r + 1] + 8 * K[r + 1]
+        out["retire"] += ret
+    return out
+
+
+def load_traffic(workload, kernel, digest):
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("{"):
+                    d = json.loads(line)
+                    if d.get("kernel_source") != digest:
+                        return None
+                    k = d.get("kernels", {}).get(kernel)
+                    return None if k is None else k.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+    return None
+
+
+def copy_probe(mib):
+    """A plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+
+
+def cpu_baseline(g, seed, budget_s):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    runs = 0
+    stats = None
+    while True:
+        _, stats = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    t = (time.perf_counter() - t0) / runs
+    tg0 = time.perf_counter()
+    oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, seed)
+    tg = time.perf_counter() - tg0
+    sum_k = int(np.sum(stats["live_pins"]))
+    return {"value": sum_k / t, "unit": "pin-incidences/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle round simulator (one thread) on the full workload, {runs} run(s) "
+                       f"of {t:.3f} s each, {stats['rounds']} rounds, sum kappa_r = {sum_k}; "
+                       f"oracle greedy on the same input: {tg:.3f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="power-law", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="auto", choices=["auto", "crcw", "crew"])
+    ap.add_argument("--rounds-per-sync", type=int, default=0)
+    ap.add_argument("--cpu-baseline", type=float, default=10.0,
+                    help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB: only run a plain device copy (PMC calibration) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this library runs on one GPU; --gpus above 1 is not supported "
+              "(batches of independent instances shard across GPUs without communication, "
+              "see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+
+    import paper_2602_22976_amd as hgm
+    import synth
+    from paper_2602_22976_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build(force=True)
+
+    fn, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = getattr(synth, fn)()
+    gen_s = time.perf_counter() - t0
+    print(f"# workload {args.workload}: n={g.n} m={g.m} kappa={g.kappa} (generated in "
+          f"{gen_s:.1f} s)", file=sys.stderr, flush=True)
+    seed = 1
+    dev = "cuda:0"
+    dg = hgm.DeviceHypergraph.from_host(g, dev)
+    opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync)
+    ws = hgm.alloc_workspace(dg, opts)
+    bits = torch.empty(max((g.m + 31) // 32, 1), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def step(timing=False):
+        return hgm.match(dg, seed, opts, workspace=ws, bits=bits, timing=timing)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: K whole steps, synchronised on both sides.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = step()
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / args.steps
+    sum_k = int(np.sum(st["live_pins"]))
+    value = sum_k / t_step
+
+    # Same steps with HIP events around every kernel (per-kernel device time).
+    tot_ms = {}
+    launches = {}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        sti = step(timing=True)
+        for k, v in sti["kernel_ms"].items():
+            tot_ms[k] = tot_ms.get(k, 0.0) + v
+            launches[k] = launches.get(k, 0) + sti["kernel_launches"][k]
+    torch.cuda.synchronize()
+    t_step_events = (time.perf_counter() - t1) / args.steps
+
+    crew_all = args.variant == "crew"
+    model = algorithmic_bytes(st, lambda r: crew_all, g.n)
+    cand = {k: tot_ms[k] for k in model if tot_ms.get(k, 0) > 0}
+    dom = max(cand, key=cand.get)
+    dom_ms = tot_ms[dom] / args.steps
+    dom_launch = launches[dom] / args.steps
+    achieved = model[dom] / (dom_ms * 1e-3) / 1e9
+    digest = kernel_source_digest()
+    traffic = load_traffic(args.workload, dom, digest)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pin-incidences/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": g.n, "m": g.m, "kappa": g.kappa,
+                   "variant": args.variant, "rounds": st["rounds"],
+                   "sum_kappa_r": sum_k, "matched": st["matched"]},
+        "input_incidences_per_s": g.kappa / t_step,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": dom, "launches_per_step": dom_launch,
+                     "ms_per_step": dom_ms, "algorithmic_bytes_per_step": model[dom],
+                     "kernel_source": digest},
+        "kernel_ms_per_step": {k: v / args.steps for k, v in tot_ms.items()},
+        "kernel_launches_per_step": {k: v / args.steps for k, v in launches.items()},
+        "ms_per_step_with_events": t_step_events * 1e3,
+        "per_round": {"live_edges": [int(x) for x in st["live_edges"]],
+                      "live_pins": [int(x) for x in st["live_pins"]],
+                      "round_ms": [round(float(x), 4) for x in sti["round_ms"]]},
+        "cpu_baseline": None,
+    }
+    if args.cpu_baseline > 0:
+        result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -88,11 +88,24 @@ typedef struct hgm_opts {
                                 remain after this many rounds; 0 = no limit */
 } hgm_opts;
 
+/* Kernel classes reported by the timing statistics. */
+#define HGM_K_SETUP 0      /* key construction, validation, hub list */
+#define HGM_K_SCATTER 1    /* round-0 edge-centric maximum (CRCW) */
+#define HGM_K_VERTEX_MAX 2 /* vertex-centric maximum (CREW) */
+#define HGM_K_TEST 3       /* local-max test and marking */
+#define HGM_K_RETIRE 4     /* retire + live-list compaction (+ next maximum in CRCW) */
+#define HGM_K_CLASSES 5
+
 /* Optional statistics (host memory).  The arrays may be NULL; when given they
  * hold `cap` entries and receive, for round r < cap: the number of live edges
- * at the start of round r, the sum of their sizes (live pin incidences), and
- * the number of edges matched in round r.  `rounds` is the number of rounds
- * run, `matched` = |M|, `weight` = w(M) (64-bit sum). */
+ * at the start of round r, the sum of their sizes (live pin incidences), the
+ * number of edges matched in round r and the sum of their sizes.  `rounds`
+ * is the number of rounds run, `matched` = |M|, `weight` = w(M) (64-bit sum).
+ * Timing (input field `timing` = 1): every kernel is bracketed by HIP events
+ * on the call's stream; kernel_ms / kernel_launches receive the summed device
+ * time and launch count per HGM_K_* class over the rounds that had live
+ * edges, and round_ms (if non-NULL) the device time of each round's kernels
+ * (its maximum, test, and the retire pass that ends it). */
 typedef struct hgm_stats {
     int32_t rounds;
     int64_t matched;
@@ -100,7 +113,12 @@ typedef struct hgm_stats {
     int64_t *live_edges;
     int64_t *live_pins;
     int64_t *matched_per_round;
+    int64_t *matched_pins;
     int32_t cap;
+    int32_t timing;
+    float *round_ms;
+    double kernel_ms[HGM_K_CLASSES];
+    int32_t kernel_launches[HGM_K_CLASSES];
 } hgm_stats;
 
 /* Bytes of device workspace hgm_match needs for this instance and options.

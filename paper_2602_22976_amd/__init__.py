@@ -41,11 +41,19 @@ class HgmOpts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32)]
 
 
+HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE = range(5)
+HGM_K_CLASSES = 5
+KERNEL_CLASS_NAMES = ["setup", "scatter", "vertex_max", "test", "retire"]
+
+
 class HgmStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("matched", ctypes.c_int64),
                 ("weight", ctypes.c_uint64), ("live_edges", ctypes.c_void_p),
                 ("live_pins", ctypes.c_void_p), ("matched_per_round", ctypes.c_void_p),
-                ("cap", ctypes.c_int32)]
+                ("matched_pins", ctypes.c_void_p), ("cap", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("round_ms", ctypes.c_void_p),
+                ("kernel_ms", ctypes.c_double * HGM_K_CLASSES),
+                ("kernel_launches", ctypes.c_int32 * HGM_K_CLASSES)]
 
 
 class HgmError(RuntimeError):
@@ -163,7 +171,7 @@ def alloc_workspace(dg: DeviceHypergraph, opts: HgmOpts | None = None):
 
 
 def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspace=None,
-          bits=None, stream=None, want_stats=True, cap=None):
+          bits=None, stream=None, want_stats=True, cap=None, timing=False):
     """Run hgm_match; returns (bits int32 tensor [ceil(m/32)], stats dict or None)."""
     torch = _torch()
     import numpy as np
@@ -175,13 +183,16 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
         bits = torch.empty(max(words, 1), dtype=torch.int32, device=dev)
     st = None
     arrays = None
-    if want_stats:
-        cap = dg.m + 1 if cap is None else cap
-        arrays = [np.zeros(max(cap, 1), dtype=np.int64) for _ in range(3)]
+    if want_stats or timing:
+        cap = min(dg.m + 1, 1 << 16) if cap is None else cap
+        arrays = [np.zeros(max(cap, 1), dtype=np.int64) for _ in range(4)]
+        rms = np.zeros(max(cap, 1), dtype=np.float32)
         st = HgmStats()
         st.cap = cap
-        st.live_edges, st.live_pins, st.matched_per_round = [
+        st.live_edges, st.live_pins, st.matched_per_round, st.matched_pins = [
             a.ctypes.data_as(ctypes.c_void_p) for a in arrays]
+        st.timing = 1 if timing else 0
+        st.round_ms = rms.ctypes.data_as(ctypes.c_void_p)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     rc = hgm_match(dg.csr(), seed, bits.data_ptr(), workspace.data_ptr(), workspace.numel(),
@@ -189,10 +200,16 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
     if rc != HGM_OK:
         raise HgmError(rc, "hgm_match")
     stats = None
-    if want_stats:
+    if st is not None:
         r = st.rounds
         k = min(r, st.cap)
         stats = {"rounds": r, "matched": st.matched, "weight": st.weight,
                  "live_edges": arrays[0][:k].copy(), "live_pins": arrays[1][:k].copy(),
-                 "matched_per_round": arrays[2][:k].copy()}
+                 "matched_per_round": arrays[2][:k].copy(),
+                 "matched_pins": arrays[3][:k].copy()}
+        if timing:
+            stats["round_ms"] = rms[:k].copy()
+            stats["kernel_ms"] = {KERNEL_CLASS_NAMES[c]: st.kernel_ms[c] for c in range(HGM_K_CLASSES)}
+            stats["kernel_launches"] = {KERNEL_CLASS_NAMES[c]: st.kernel_launches[c]
+                                        for c in range(HGM_K_CLASSES)}
     return bits[:words], stats

@@ -17,17 +17,28 @@ constexpr int kDefaultRoundsPerSync = 4;
 constexpr int kMaxRoundsPerSync = 200;
 constexpr int kDefaultHubThreshold = 8192;
 constexpr int kBlocksPerCu = 8;
+constexpr int kEdgeGrid = 2048;  // workgroups of the edge kernels (fixed, device independent)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t key, best0, best1, done, list0, list1, slots, err, live_key, hubs, hub_count,
-        hub_piece_off, vbits, total;
-    int ring;
+    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, pieces,
+        piece_count, hot, vbits, total;
+    int ring, grid, region, piece_cap;
 };
+
+// Edge schedule: `grid` workgroups, each owning `region` consecutive edge ids
+// (a multiple of kBlock); grid * region >= m.
+void edge_schedule(int64_t m, int *grid, int *region) {
+    const int64_t chunks = std::max<int64_t>(1, (m + kBlock - 1) / kBlock);
+    const int64_t g = std::min<int64_t>(kEdgeGrid, chunks);
+    *grid = (int)g;
+    *region = (int)(((chunks + g - 1) / g) * kBlock);
+}
 
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
+    bool have_vertex_side;  // v_off / v_edges given
 };
 
 int resolve_opts(const hgm_opts *in, Opts *o) {
@@ -45,13 +56,18 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     return HGM_OK;
 }
 
-// Whether the vertex-centric form runs in round r.
+// Whether the vertex-centric form runs in round r.  AUTO: round 0, where every
+// edge is live and the vertex pass needs no atomics, when the vertex side is
+// given; the edge-centric form afterwards, since it touches only the pins of
+// live edges while the vertex pass would scan every open vertex's full list.
 bool crew_round(const Opts &o, int r) {
-    (void)r;
-    return o.variant == HGM_VARIANT_CREW;
+    if (o.variant == HGM_VARIANT_CREW) return true;
+    if (o.variant == HGM_VARIANT_AUTO) return r == 0 && o.have_vertex_side;
+    return false;
 }
 
-bool uses_crew(const Opts &o) { return o.variant == HGM_VARIANT_CREW; }
+bool any_crew_round(const Opts &o) { return crew_round(o, 0); }
+bool uses_live_key(const Opts &o) { return o.variant == HGM_VARIANT_CREW; }
 
 Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o) {
     Layout L;
@@ -62,25 +78,34 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o) {
         return p;
     };
     L.ring = o.rounds_per_sync + 2;
+    edge_schedule(m, &L.grid, &L.region);
+    const size_t cap = (size_t)L.grid * (size_t)L.region;
     L.key = take(8 * (size_t)m);
     L.best0 = take(8 * (size_t)n);
     L.best1 = take(8 * (size_t)n);
     L.done = take((size_t)n);
-    L.list0 = take(4 * (size_t)m);
-    L.list1 = take(4 * (size_t)m);
-    L.slots = take(sizeof(RoundSlot) * (size_t)L.ring);
+    L.list0 = take(4 * cap);
+    L.list1 = take(4 * cap);
+    L.cnt0 = take(4 * (size_t)L.grid);
+    L.cnt1 = take(4 * (size_t)L.grid);
+    L.stats = take(sizeof(RoundStats) * (size_t)L.ring);
     L.err = take(4);
-    const bool crew = uses_crew(o);
-    L.live_key = take(crew ? 8 * (size_t)m : 0);
-    L.hubs = take(crew ? 4 * (size_t)n : 0);
-    L.hub_count = take(4);
-    L.hub_piece_off = take(crew ? 4 * ((size_t)n + 1) : 0);
+    L.live_key = take(uses_live_key(o) ? 8 * (size_t)m : 0);
+    // pieces: each vertex of degree d > T gives ceil(d / P) <= d / P + 1 pieces,
+    // and there are fewer than kappa / T such vertices.
+    L.piece_cap = any_crew_round(o)
+                      ? (int)std::min<int64_t>(kappa / kHubPiece + kappa / o.hub_threshold + 1,
+                                               ((int64_t)1 << 31) - 1)
+                      : 0;
+    L.pieces = take(sizeof(int2) * (size_t)L.piece_cap);
+    L.piece_count = take(4);
+    L.hot = take(8 * (size_t)kSub);
     L.vbits = take(o.validate ? 4 * (size_t)((kappa + 31) / 32) : 0);
     L.total = at;
     return L;
 }
 
-State carve(void *ws, const Layout &L) {
+State carve(void *ws, const Layout &L, const Opts &o) {
     char *b = (char *)ws;
     State s;
     s.key = (uint64_t *)(b + L.key);
@@ -89,15 +114,25 @@ State carve(void *ws, const Layout &L) {
     s.done = (uint8_t *)(b + L.done);
     s.list[0] = (int32_t *)(b + L.list0);
     s.list[1] = (int32_t *)(b + L.list1);
-    s.slots = (RoundSlot *)(b + L.slots);
+    s.cnt[0] = (int32_t *)(b + L.cnt0);
+    s.cnt[1] = (int32_t *)(b + L.cnt1);
+    s.stats = (RoundStats *)(b + L.stats);
     s.ring = L.ring;
+    s.grid = L.grid;
+    s.region = L.region;
     s.err = (int32_t *)(b + L.err);
     s.live_key = (uint64_t *)(b + L.live_key);
-    s.hubs = (int32_t *)(b + L.hubs);
-    s.hub_count = (int32_t *)(b + L.hub_count);
-    s.hub_piece_off = (int32_t *)(b + L.hub_piece_off);
+    s.pieces = (int2 *)(b + L.pieces);
+    s.piece_count = (int32_t *)(b + L.piece_count);
+    s.hot = (unsigned long long *)(b + L.hot);
+    s.piece_cap = L.piece_cap;
+    s.hub_threshold = o.hub_threshold;
     s.vbits = (uint32_t *)(b + L.vbits);
     return s;
+}
+
+void bind_graph(Opts *o, const hgm_csr *g) {
+    o->have_vertex_side = g && g->v_off && (g->kappa == 0 || (g->v_edges && g->n > 0));
 }
 
 int check_graph(const hgm_csr *g, const Opts &o) {
@@ -107,7 +142,7 @@ int check_graph(const hgm_csr *g, const Opts &o) {
     if (g->m > 0 && (!g->e_off || !g->w)) return HGM_E_ARG;
     if (g->kappa > 0 && !g->e_pins) return HGM_E_ARG;
     if (g->kappa > 0 && g->m == 0) return HGM_E_ARG;
-    if (uses_crew(o) || o.validate) {
+    if (o.variant == HGM_VARIANT_CREW || o.validate) {
         if (!g->v_off) return HGM_E_ARG;
         if (g->kappa > 0 && (!g->v_edges || g->n == 0)) return HGM_E_ARG;
     }
@@ -127,6 +162,76 @@ int device_grid() {
     if (dev >= 0 && dev < 64) cached[dev] = grid;
     return grid;
 }
+
+// Optional per-kernel timing: an event is recorded after every kernel (and
+// one before the first); consecutive events bracket one kernel on the stream.
+// Events are kept in a per-thread pool and reused across calls.
+struct KernelTimer {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    std::vector<int> cls, round;  // per bracketed kernel
+    size_t used = 0;              // events recorded since the last harvest
+    static std::vector<hipEvent_t> &pool() {
+        static thread_local std::vector<hipEvent_t> p;
+        return p;
+    }
+    hipError_t event(size_t i, hipEvent_t *ev) {
+        auto &p = pool();
+        while (p.size() <= i) {
+            hipEvent_t e;
+            hipError_t rc = hipEventCreate(&e);
+            if (rc != hipSuccess) return rc;
+            p.push_back(e);
+        }
+        *ev = p[i];
+        return hipSuccess;
+    }
+    hipError_t start() {
+        if (!on) return hipSuccess;
+        used = 0;
+        cls.clear();
+        round.clear();
+        hipEvent_t e;
+        hipError_t rc = event(used, &e);
+        if (rc != hipSuccess) return rc;
+        used = 1;
+        return hipEventRecord(e, stream);
+    }
+    hipError_t after(int c, int r) {
+        if (!on) return hipSuccess;
+        hipEvent_t e;
+        hipError_t rc = event(used, &e);
+        if (rc != hipSuccess) return rc;
+        cls.push_back(c);
+        round.push_back(r);
+        used += 1;
+        return hipEventRecord(e, stream);
+    }
+    // After a stream synchronisation: add the bracketed durations of kernels
+    // of rounds < live_rounds (round -1 = setup) and restart from the last event.
+    hipError_t harvest(int live_rounds, hgm_stats *st, std::vector<float> &round_ms) {
+        if (!on) return hipSuccess;
+        auto &p = pool();
+        for (size_t i = 0; i < cls.size(); ++i) {
+            float ms = 0.f;
+            hipError_t rc = hipEventElapsedTime(&ms, p[i], p[i + 1]);
+            if (rc != hipSuccess) return rc;
+            const int r = round[i];
+            if (r >= live_rounds) continue;
+            st->kernel_ms[cls[i]] += ms;
+            st->kernel_launches[cls[i]] += 1;
+            if (r >= 0) {
+                if ((size_t)r >= round_ms.size()) round_ms.resize(r + 1, 0.f);
+                round_ms[r] += ms;
+            }
+        }
+        std::swap(p[0], p[used - 1]);
+        used = 1;
+        cls.clear();
+        round.clear();
+        return hipSuccess;
+    }
+};
 
 #define HGM_TRY(expr)                                   \
     do {                                                \
@@ -154,6 +259,7 @@ const char *hgm_strerror(int code) {
 size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts) {
     Opts o;
     if (resolve_opts(opts, &o) != HGM_OK || !g) return 0;
+    bind_graph(&o, g);
     if (g->n < 0 || g->m < 0 || g->kappa < 0 || g->kappa >= ((int64_t)1 << 31)) return 0;
     return make_layout(g->n, g->m, g->kappa, o).total;
 }
@@ -165,10 +271,9 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     if (rc != HGM_OK) return rc;
     rc = check_graph(gin, o);
     if (rc != HGM_OK) return rc;
+    bind_graph(&o, gin);
     if (gin->m > 0 && !matched_bits) return HGM_E_ARG;
-    if (stats && stats->cap > 0 &&
-        (!stats->live_edges || !stats->live_pins || !stats->matched_per_round))
-        return HGM_E_ARG;
+    if (stats && stats->cap < 0) return HGM_E_ARG;
     const Layout lay = make_layout(gin->n, gin->m, gin->kappa, o);
     if (!workspace) return HGM_E_ARG;
     if (ws_bytes < lay.total) return HGM_E_SIZE;
@@ -183,35 +288,60 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     g.v_off = gin->v_off;
     g.v_edges = gin->v_edges;
     g.w = gin->w;
-    const State s = carve(workspace, lay);
+    const State s = carve(workspace, lay, o);
     Launch L;
     L.grid = device_grid();
     L.stream = (hipStream_t)stream;
     if (L.grid <= 0) return HGM_E_HIP;
 
-    const bool crew = uses_crew(o);
-    HGM_TRY(launch_init(L, g, seed, s, matched_bits, crew ? 1 : 0));
+    int init_flags = 0;
+    if (uses_live_key(o)) init_flags |= kInitLiveKey;
+    if (any_crew_round(o)) init_flags |= kInitHubs;
+    KernelTimer T;
+    T.on = stats && stats->timing;
+    T.stream = L.stream;
+    if (stats) {
+        for (int c = 0; c < HGM_K_CLASSES; ++c) {
+            stats->kernel_ms[c] = 0.0;
+            stats->kernel_launches[c] = 0;
+        }
+    }
+    std::vector<float> round_ms;
+    constexpr int kSetup = -1;
+    HGM_TRY(T.start());
+    HGM_TRY(launch_init(L, g, seed, s, matched_bits, init_flags));
+    HGM_TRY(T.after(HGM_K_SETUP, kSetup));
     if (o.validate) {
         HGM_TRY(launch_validate(L, g, s, 1));
+        HGM_TRY(T.after(HGM_K_SETUP, kSetup));
         int32_t err = 0;
         HGM_TRY(hipMemcpyAsync(&err, s.err, sizeof(err), hipMemcpyDeviceToHost, L.stream));
         HGM_TRY(hipStreamSynchronize(L.stream));
+        HGM_TRY(T.harvest(1, stats, round_ms));
         if (err) return HGM_E_CSR;
     }
 
-    std::vector<RoundSlot> ring(lay.ring);
-    std::vector<int64_t> live_e, live_p, matched_r;
+    std::vector<RoundStats> ring(lay.ring);
+    std::vector<int64_t> live_e, live_p, matched_r, matched_p;
     std::vector<uint64_t> weight_r;
     live_e.push_back(g.m);
     live_p.push_back(g.kappa);
 
     int rounds = 0;
+    int max0_event = -1;  // timer entry of the AUTO round-0 maximum (class fixed after the sync)
     bool finished = g.m == 0;
     if (!finished) {
-        if (crew_round(o, 0))
-            HGM_TRY(launch_vertex_max(L, g, s, 0, o.hub_threshold));
-        else
-            HGM_TRY(launch_scatter(L, g, s, 0));
+        if (o.variant == HGM_VARIANT_AUTO && o.have_vertex_side) {
+            HGM_TRY(launch_max0(L, g, s, seed));
+            max0_event = (int)T.cls.size();
+            HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
+        } else if (crew_round(o, 0)) {
+            HGM_TRY(launch_vertex_max(L, g, s, 0, seed));
+            HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
+        } else {
+            HGM_TRY(launch_scatter(L, g, s));
+            HGM_TRY(T.after(HGM_K_SCATTER, 0));
+        }
     }
     int launched = 0;  // rounds whose test has been enqueued
     while (!finished) {
@@ -222,31 +352,46 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
         for (int b = 0; b < batch; ++b) {
             const int r = launched;
             const bool next_crew = crew_round(o, r + 1);
-            const bool cur_crew = crew_round(o, r);
             // Clear the next round's max buffer when the next round scatters
             // (always in CRCW; at the switch from CREW to CRCW).
             HGM_TRY(launch_test(L, g, s, r, next_crew ? 0 : 1, matched_bits));
-            (void)cur_crew;
+            HGM_TRY(T.after(HGM_K_TEST, r));
             HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1));
-            if (next_crew) HGM_TRY(launch_vertex_max(L, g, s, r + 1, o.hub_threshold));
+            HGM_TRY(T.after(HGM_K_RETIRE, r));
+            if (next_crew) {
+                HGM_TRY(launch_vertex_max(L, g, s, r + 1, seed));
+                HGM_TRY(T.after(HGM_K_VERTEX_MAX, r + 1));
+            }
             launched += 1;
         }
-        HGM_TRY(hipMemcpyAsync(ring.data(), s.slots, sizeof(RoundSlot) * lay.ring,
+        HGM_TRY(hipMemcpyAsync(ring.data(), s.stats, sizeof(RoundStats) * lay.ring,
                                hipMemcpyDeviceToHost, L.stream));
         HGM_TRY(hipStreamSynchronize(L.stream));
+        auto sum = [](const unsigned long long *a) {
+            unsigned long long t = 0;
+            for (int i = 0; i < kSub; ++i) t += a[i];
+            return t;
+        };
         for (int r = first; r < launched; ++r) {
-            const RoundSlot &cur = ring[r % lay.ring];
-            const RoundSlot &nxt = ring[(r + 1) % lay.ring];
-            matched_r.push_back(cur.matched);
-            weight_r.push_back(cur.weight);
-            if (nxt.live == 0) {
+            const RoundStats &cur = ring[r % lay.ring];
+            const RoundStats &nxt = ring[(r + 1) % lay.ring];
+            matched_r.push_back((int64_t)sum(cur.matched));
+            weight_r.push_back(sum(cur.weight));
+            matched_p.push_back((int64_t)sum(cur.mpins));
+            const unsigned long long live_next = sum(nxt.live);
+            if (live_next == 0) {
                 finished = true;
                 rounds = r + 1;
                 break;
             }
-            live_e.push_back(nxt.live);
-            live_p.push_back(nxt.kappa);
+            live_e.push_back((int64_t)live_next);
+            live_p.push_back((int64_t)sum(nxt.kappa));
         }
+        if (max0_event >= 0 && T.on && max0_event < (int)T.cls.size()) {
+            T.cls[max0_event] = ring[0].form == 1 ? HGM_K_SCATTER : HGM_K_VERTEX_MAX;
+            max0_event = -1;
+        }
+        HGM_TRY(T.harvest(finished ? rounds : launched + 1, stats, round_ms));
         if (!finished && o.max_rounds > 0 && launched >= o.max_rounds) return HGM_E_ROUND_LIMIT;
     }
 
@@ -258,9 +403,11 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
             tm += matched_r[r];
             tw += weight_r[r];
             if (r < stats->cap) {
-                stats->live_edges[r] = live_e[r];
-                stats->live_pins[r] = live_p[r];
-                stats->matched_per_round[r] = matched_r[r];
+                if (stats->live_edges) stats->live_edges[r] = live_e[r];
+                if (stats->live_pins) stats->live_pins[r] = live_p[r];
+                if (stats->matched_per_round) stats->matched_per_round[r] = matched_r[r];
+                if (stats->matched_pins) stats->matched_pins[r] = matched_p[r];
+                if (stats->round_ms) stats->round_ms[r] = r < (int)round_ms.size() ? round_ms[r] : 0.f;
             }
         }
         stats->matched = tm;

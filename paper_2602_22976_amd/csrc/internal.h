@@ -9,14 +9,20 @@
 namespace hgm {
 
 constexpr int kBlock = 256;  // threads per workgroup = edges (or vertices) per chunk
+constexpr int kSub = 64;     // counters are spread over kSub addresses (one per 64 blocks)
+constexpr int kHubPiece = 8192;  // incidences of a hub vertex reduced by one workgroup
+constexpr int kHotDegree = 64;   // vertices at least this degree count as hot (round-0 choice)
 
-// Per-round counters, kept in a small device ring indexed by round % ring size.
-struct RoundSlot {
-    int32_t live;     // live edges at the start of the round (|L_r|)
-    int32_t pad;
-    int64_t kappa;    // sum of their sizes (kappa_r)
-    int64_t matched;  // edges matched in the round
-    uint64_t weight;  // their total weight
+// Per-round counters, in a small device ring indexed by round % ring.  Every
+// field is split into kSub partial sums (block b adds into entry b % kSub)
+// so that no single address takes one atomic per workgroup; the host sums.
+struct RoundStats {
+    unsigned long long live[kSub];     // live edges at the start of the round (|L_r|)
+    unsigned long long kappa[kSub];    // sum of their sizes (kappa_r)
+    unsigned long long matched[kSub];  // edges matched in the round
+    unsigned long long weight[kSub];   // their total weight
+    unsigned long long mpins[kSub];    // their total size
+    unsigned long long form;           // round 0 only: 1 edge-centric, 2 vertex-centric maximum
 };
 
 struct Graph {
@@ -30,34 +36,52 @@ struct Graph {
 };
 
 // Device state of one hgm_match call, carved out of the caller's workspace.
+//
+// Live edges are kept per workgroup: edge kernels run exactly `grid`
+// workgroups, and workgroup b owns the edges with ids in
+// [b * region, (b + 1) * region).  Its live edges of round r sit in
+// list[r & 1][b * region ...] with count cnt[r & 1][b]; round 0 is the
+// identity.  Compaction is therefore local to a workgroup and needs no
+// global atomic, and an edge stays with the same workgroup for the whole run.
 struct State {
     uint64_t *key;      // [m] packed key w<<32 | H(seed, e)
     uint64_t *best[2];  // [n] per-vertex maximum live key, double-buffered by round parity
     uint8_t *done;      // [n] vertex is a pin of a matched edge
-    int32_t *list[2];   // [m] compacted live-edge lists, by round parity
-    RoundSlot *slots;   // [ring]
+    int32_t *list[2];   // [grid * region] live edges per workgroup region
+    int32_t *cnt[2];    // [grid] live edges per region
+    RoundStats *stats;  // [ring]
     int32_t ring;
+    int32_t grid;       // edge-kernel workgroups
+    int32_t region;     // edge ids (and list capacity) per workgroup, multiple of kBlock
     int32_t *err;       // [1] validation error flag
-    // CREW (vertex-centric) extras
-    uint64_t *live_key; // [m] key while live, 0 once matched or retired
-    int32_t *hubs;      // [n] vertices whose max is split over workgroups
-    int32_t *hub_count; // [1]
-    int32_t *hub_piece_off; // [n+1] piece offsets of the hubs
+    // Vertex-centric (CREW) extras
+    uint64_t *live_key; // [m] key while live, 0 once matched or retired (CREW variant)
+    int2 *pieces;       // [piece_cap] (hub vertex, piece index): the incidence list of a
+                        // vertex of degree > hub threshold is cut into kHubPiece pieces
+    int32_t *piece_count;  // [1]
+    unsigned long long *hot;  // [kSub] incidences on vertices of degree >= kHotDegree
+    int32_t piece_cap;
+    int32_t hub_threshold;
     uint32_t *vbits;    // [ceil(kappa/32)] validation: edge-side incidences seen
 };
 
 struct Launch {
-    int grid;            // persistent workgroup count
+    int grid;            // persistent workgroup count for vertex / setup kernels
     hipStream_t stream;
 };
 
+// init_flags: which optional setup k_init performs.
+constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
+constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
-                       uint32_t *bits, int crew);
+                       uint32_t *bits, int init_flags);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
-hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, int round);
+hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s);
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
-                             int hub_threshold);
+                             uint32_t seed);
+// Round-0 maximum in the form chosen from the degree profile (AUTO).
+hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed);
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
                        uint32_t *bits);
 

@@ -17,9 +17,12 @@
 // size distribution (Zipf sizes up to 64 cost no more lanes than they use),
 // and consecutive lanes read consecutive pins.
 //
-// Round r uses list[r & 1] (round 0 uses the identity list 0..m-1) and the
-// counters slots[r % ring].  best[] is double-buffered by round parity so that
-// the test of round r can clear the buffer round r+1 will fill.
+// Edge kernels run exactly s.grid workgroups; workgroup b owns the edge ids
+// [b * region, (b + 1) * region) for the whole run and keeps its live ones in
+// its own region of list[r & 1] (round 0: the identity).  Counters of round r
+// go to stats[r % ring], spread over kSub addresses.  best[] is
+// double-buffered by round parity so that the test of round r can clear the
+// buffer round r+1 will fill.
 #include "internal.h"
 
 namespace hgm {
@@ -102,8 +105,13 @@ __device__ __forceinline__ int find_item(const int *start, int t) {
     return j;
 }
 
-__device__ __forceinline__ uint64_t load_relaxed(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Read of a best[] entry that other workgroups raise with atomics during the
+// same pass.  Workgroup scope lets the load hit in L2 (an agent-scope load
+// bypasses it on this chip); the value may be stale, but best[] only grows
+// within a pass, so a stale value is a lower bound and skipping the atomic
+// when it is already >= the key is still exact.
+__device__ __forceinline__ uint64_t load_lower_bound(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ void atomic_max_u64(uint64_t *p, uint64_t v) {
@@ -118,13 +126,65 @@ struct ChunkLds {
     int flag[kBlock];         // per-item flag (failed test / retired)
     int wave_tmp[kWaves];
     unsigned long long sum_tmp[kWaves];
-    int out_base;
 };
 
+// Incidences a lane visits per step of a flattened loop.  Their pin loads and
+// the gathers that follow are independent, so a lane keeps this many memory
+// requests in flight instead of one.
+constexpr int kUnroll = 4;
+
+// The kUnroll incidences t0, t0 + kBlock, ... of the current chunk: item
+// index j (-1 past the end) and pin.
+__device__ __forceinline__ void chunk_pins(const ChunkLds &L, const int32_t *e_pins, int total,
+                                           int t0, int (&j)[kUnroll], int (&pin)[kUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int t = t0 + u * kBlock;
+        j[u] = t < total ? find_item(L.start, t) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+        pin[u] = j[u] >= 0 ? e_pins[L.base[j[u]] + (t0 + u * kBlock - L.start[j[u]])] : 0;
+}
+
+// Raises best[pin] to the chunk items' keys over a flattened loop.  The
+// plain read first skips the atomic when the slot already holds a larger key
+// (best only grows during the pass, so a stale read is merely cautious).
+// One incidence per lane and step: issuing more reads before the atomics
+// makes more of them see stale values and turns filtered reads into atomics,
+// which cost far more on this hardware than the latency saved.
+__device__ __forceinline__ void scatter_chunk(const ChunkLds &L, const int32_t *e_pins, int total,
+                                              uint64_t *best) {
+    for (int t = threadIdx.x; t < total; t += kBlock) {
+        const int j = find_item(L.start, t);
+        const int pin = e_pins[L.base[j] + (t - L.start[j])];
+        const uint64_t k = L.key[j];
+        if (load_lower_bound(&best[pin]) < k) atomic_max_u64(&best[pin], k);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Setup: keys, cleared per-vertex state, cleared bitmap, round-0 counters.
+// Prologue (one workgroup): round counters, error flag, hub piece counter.
+__global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
+    unsigned long long *st = (unsigned long long *)s.stats;
+    const int words = s.ring * (int)(sizeof(RoundStats) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < words; i += blockDim.x) st[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.stats[0].live[0] = (unsigned long long)g.m;
+        s.stats[0].kappa[0] = g.m > 0 ? (unsigned long long)g.e_off[g.m] : 0ull;
+        *s.err = 0;
+        *s.piece_count = 0;
+    }
+    if (threadIdx.x < kSub) s.hot[threadIdx.x] = 0;
+}
+
+// Setup: keys, cleared per-vertex state and bitmap; optionally the CREW live
+// keys and the pieces of high-degree vertices.
 __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s, uint32_t *bits,
-                                                 int crew) {
+                                                 int flags) {
+    __shared__ unsigned long long sum_tmp[kWaves];
+    unsigned long long hot = 0;
     const int64_t words = ((int64_t)g.m + 31) / 32;
     const int64_t span = g.m > g.n ? g.m : g.n;
     const int64_t top = span > words ? span : words;
@@ -133,25 +193,27 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
         if (i < g.m) {
             uint64_t k = ((uint64_t)g.w[i] << 32) | priority_hash(seed, (uint32_t)i);
             s.key[i] = k;
-            if (crew) s.live_key[i] = k;
+            if (flags & kInitLiveKey) s.live_key[i] = k;
         }
         if (i < g.n) {
             s.best[0][i] = 0;
             s.done[i] = 0;
+            if (flags & kInitHubs) {
+                const int deg = g.v_off[i + 1] - g.v_off[i];
+                if (deg >= kHotDegree) hot += (unsigned long long)deg;
+                if (deg > s.hub_threshold) {
+                    const int np = (deg + kHubPiece - 1) / kHubPiece;
+                    const int q0 = atomicAdd(s.piece_count, np);
+                    for (int k = 0; k < np && q0 + k < s.piece_cap; ++k)
+                        s.pieces[q0 + k] = make_int2((int)i, k);
+                }
+            }
         }
         if (i < words) bits[i] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x < s.ring) {
-        RoundSlot z = {0, 0, 0, 0, 0};
-        if (threadIdx.x == 0) {
-            z.live = g.m;
-            z.kappa = g.m > 0 ? g.e_off[g.m] : 0;
-        }
-        s.slots[threadIdx.x] = z;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *s.err = 0;
-        if (crew) *s.hub_count = 0;
+    if (flags & kInitHubs) {
+        hot = block_sum_u64(hot, sum_tmp);
+        if (threadIdx.x == 0 && hot) atomicAdd(&s.hot[blockIdx.x % kSub], hot);
     }
 }
 
@@ -200,69 +262,35 @@ __global__ void __launch_bounds__(kBlock) k_validate(Graph g, State s, int check
 }
 
 // ---------------------------------------------------------------------------
+// Region helpers: number of live edges of workgroup b in round r, and item i.
+__device__ __forceinline__ int region_count(const State &s, int m, int round, int b) {
+    if (round == 0) {
+        const int64_t lo = (int64_t)b * s.region;
+        const int64_t c = (int64_t)m - lo;
+        return c <= 0 ? 0 : (c > s.region ? s.region : (int)c);
+    }
+    return s.cnt[round & 1][b];
+}
+
+__device__ __forceinline__ int region_item(const State &s, int round, int b, int i) {
+    const int64_t at = (int64_t)b * s.region + i;
+    return round == 0 ? (int)at : s.list[round & 1][at];
+}
+
+// ---------------------------------------------------------------------------
 // Edge-centric scatter of round 0 (Algorithm 1, per-vertex maximum by
 // concurrent writes): every edge raises best[pin] to its key at each pin.
 // The plain read first skips the atomic when the slot already holds a larger
 // key; best only grows during the pass, so a stale read is merely cautious.
-__global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s) {
-    __shared__ ChunkLds L;
+__device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b) {
     uint64_t *best = s.best[0];
-    const int m = g.m;
-    for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < m; c0 += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)c0 + threadIdx.x;
+    const int cnt = region_count(s, g.m, 0, b);
+    for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+        const int i = c0 + threadIdx.x;
         int len = 0, base = 0;
         uint64_t key = 0;
-        if (i < m) {
-            base = g.e_off[i];
-            len = g.e_off[i + 1] - base;
-            key = s.key[i];
-        }
-        int total;
-        int st = block_exclusive_sum(len, L.wave_tmp, &total);
-        L.start[threadIdx.x] = st;
-        L.base[threadIdx.x] = base;
-        L.key[threadIdx.x] = key;
-        __syncthreads();
-        for (int t = threadIdx.x; t < total; t += kBlock) {
-            int j = find_item(L.start, t);
-            int pin = g.e_pins[L.base[j] + (t - L.start[j])];
-            uint64_t k = L.key[j];
-            if (load_relaxed(&best[pin]) < k) atomic_max_u64(&best[pin], k);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Retire + compact (+ scatter) for round r >= 1.  Input: the live list of
-// round r-1 (identity for r-1 = 0) and its count.  An edge of that list
-// survives iff it is non-empty and none of its pins is done; this removes the
-// edges matched in round r-1 (all their pins are done) and every edge that
-// touches them (Algorithm 2's OR-reduction over the pins of each edge).
-// Survivors are appended to list[r & 1] (one atomic per chunk) and counted
-// into slots[r].  Then, depending on the variant:
-//   scatter = 1 (CRCW): each survivor raises best[r & 1][pin] at its pins.
-//   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
-//                       vertices' best[r & 1] is cleared for the vertex pass.
-__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter) {
-    __shared__ ChunkLds L;
-    const RoundSlot *in_slot = &s.slots[(round - 1) % s.ring];
-    RoundSlot *out_slot = &s.slots[round % s.ring];
-    const int32_t *in_list = (round - 1 == 0) ? nullptr : s.list[(round - 1) & 1];
-    int32_t *out_list = s.list[round & 1];
-    uint64_t *best = s.best[round & 1];
-    const int cnt = in_slot->live;
-
-    if (!scatter && blockIdx.x == 0) {
-        const int h = *s.hub_count;
-        for (int i = threadIdx.x; i < h; i += kBlock) best[s.hubs[i]] = 0;
-    }
-    for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < cnt; c0 += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)c0 + threadIdx.x;
-        int e = -1, len = 0, base = 0;
-        uint64_t key = 0;
         if (i < cnt) {
-            e = in_list ? in_list[i] : i;
+            const int e = region_item(s, 0, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
             key = s.key[e];
@@ -272,38 +300,92 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         L.start[threadIdx.x] = st;
         L.base[threadIdx.x] = base;
         L.key[threadIdx.x] = key;
-        L.flag[threadIdx.x] = 0;
         __syncthreads();
-        for (int t = threadIdx.x; t < total; t += kBlock) {
-            int j = find_item(L.start, t);
-            int pin = g.e_pins[L.base[j] + (t - L.start[j])];
-            if (s.done[pin]) L.flag[j] = 1;
+        scatter_chunk(L, g.e_pins, total, best);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s) {
+    __shared__ ChunkLds L;
+    scatter0_region(g, s, L, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Retire + compact (+ scatter) for round r >= 1.  Input: workgroup b's live
+// edges of round r-1.  An edge survives iff it is non-empty and none of its
+// pins is done; this removes the edges matched in round r-1 (all their pins
+// are done) and every edge that touches them (Algorithm 2's OR-reduction over
+// the pins of each edge).  Survivors are compacted, in order, into the
+// workgroup's region of list[r & 1]; the count goes to cnt[r & 1][b] and the
+// round's counters.  Then, depending on the variant:
+//   scatter = 1 (CRCW): each survivor raises best[r & 1][pin] at its pins.
+//   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
+//                       vertices' best[r & 1] is cleared for the vertex pass.
+__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter) {
+    __shared__ ChunkLds L;
+    const int b = blockIdx.x;
+    const int cnt = region_count(s, g.m, round - 1, b);
+    int32_t *out_list = s.list[round & 1] + (int64_t)b * s.region;
+    uint64_t *best = s.best[round & 1];
+    RoundStats *st_out = &s.stats[round % s.ring];
+
+    if (!scatter && b == 0) {
+        const int np = min(*s.piece_count, s.piece_cap);
+        for (int q = threadIdx.x; q < np; q += kBlock) {
+            const int2 pc = s.pieces[q];
+            if (pc.y == 0) best[pc.x] = 0;
         }
-        __syncthreads();
-        const int alive = (e >= 0 && len > 0 && !L.flag[threadIdx.x]) ? 1 : 0;
+    }
+    int out_pos = 0;                 // survivors written so far (uniform)
+    unsigned long long kap_acc = 0;  // their pins (thread 0's copy is the total)
+    for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+        const int i = c0 + threadIdx.x;
+        int e = -1, len = 0, base = 0;
+        uint64_t key = 0;
+        if (i < cnt) {
+            e = region_item(s, round - 1, b, i);
+            base = g.e_off[e];
+            len = g.e_off[e + 1] - base;
+            key = s.key[e];
+        }
+        // One lane per edge, stopping at the first done pin: most retired
+        // edges are found after one or two reads, survivors read all pins.
+        bool dead = false;
+        for (int k0 = 0; k0 < len && !dead; k0 += kUnroll) {
+            int p[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] : -1;
+            uint8_t dv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) dv[u] = p[u] >= 0 ? s.done[p[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) dead |= dv[u] != 0;
+        }
+        const int alive = (e >= 0 && len > 0 && !dead) ? 1 : 0;
+        L.base[threadIdx.x] = base;
+        L.key[threadIdx.x] = key;
         if (!scatter && e >= 0 && !alive) s.live_key[e] = 0;
         int n_alive;
         int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
-        unsigned long long kap = block_sum_u64(alive ? (unsigned long long)len : 0ull, L.sum_tmp);
-        if (threadIdx.x == 0 && n_alive > 0) {
-            L.out_base = atomicAdd(&out_slot->live, n_alive);
-            atomicAdd((unsigned long long *)&out_slot->kappa, kap);
-        }
-        __syncthreads();
-        if (alive) out_list[L.out_base + pos] = e;
+        if (alive) out_list[out_pos + pos] = e;
+        out_pos += n_alive;
+        int total2;
+        int st2 = block_exclusive_sum(alive ? len : 0, L.wave_tmp, &total2);
+        kap_acc += (unsigned long long)total2;
         if (scatter) {
-            int total2;
-            int st2 = block_exclusive_sum(alive ? len : 0, L.wave_tmp, &total2);
             L.start[threadIdx.x] = st2;
             __syncthreads();
-            for (int t = threadIdx.x; t < total2; t += kBlock) {
-                int j = find_item(L.start, t);
-                int pin = g.e_pins[L.base[j] + (t - L.start[j])];
-                uint64_t k = L.key[j];
-                if (load_relaxed(&best[pin]) < k) atomic_max_u64(&best[pin], k);
-            }
+            scatter_chunk(L, g.e_pins, total2, best);
         }
         __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        s.cnt[round & 1][b] = out_pos;
+        if (out_pos > 0) {
+            atomicAdd(&st_out->live[b % kSub], (unsigned long long)out_pos);
+            atomicAdd(&st_out->kappa[b % kSub], kap_acc);
+        }
     }
 }
 
@@ -313,34 +395,34 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // vertices and split hubs contribute no incidences; the chunk's incidences
 // are flattened over the lanes, each wave reduces runs of equal vertex with a
 // segmented max-scan in registers, and one LDS atomic per run and wave
-// combines the runs.  Hubs (degree > hub_threshold) are cut into pieces of
+// combines the runs.  Hubs (degree > hub threshold) are cut into pieces of
 // kHubPiece incidences, each reduced by one workgroup and combined with one
-// global atomic max (their best was cleared by the retire pass).
-constexpr int kHubPiece = 8192;
+// global atomic max (their best was cleared by init or the retire pass).
+// Round 0 has no retired edge yet: keys are rebuilt from the weights
+// (w << 32 | H(seed, e)), gathering 4 bytes per incidence instead of 8;
+// later rounds gather live_key (0 once the edge left the live set).
+__device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
+                                               uint32_t seed, int e) {
+    if (round == 0) return ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)e);
+    return s.live_key[e];
+}
 
-__global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, int hub_threshold) {
-    __shared__ ChunkLds L;
+__device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, ChunkLds &L,
+                                                int round, uint32_t seed) {
     uint64_t *best = s.best[round & 1];
     const int lane = threadIdx.x & (kWave - 1);
+    const int hub_threshold = s.hub_threshold;
 
-    // Hub pieces first.  Piece q belongs to the hub h with
-    // hub_piece_off[h] <= q < hub_piece_off[h+1] and covers kHubPiece
-    // incidences of its list; pieces are spread over all workgroups.
-    const int nh = *s.hub_count;
-    const int n_pieces = nh > 0 ? s.hub_piece_off[nh] : 0;
+    const int n_pieces = min(*s.piece_count, s.piece_cap);
     for (int q = blockIdx.x; q < n_pieces; q += gridDim.x) {
-        int lo = 0, hi = nh - 1;  // last h with hub_piece_off[h] <= q
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s.hub_piece_off[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        const int v = s.hubs[lo];
+        const int2 pc = s.pieces[q];
+        const int v = pc.x;
         if (s.done[v]) continue;
-        const int p0 = g.v_off[v] + (q - s.hub_piece_off[lo]) * kHubPiece;
+        const int p0 = g.v_off[v] + pc.y * kHubPiece;
         const int p1 = min(g.v_off[v + 1], p0 + kHubPiece);
         uint64_t mx = 0;
         for (int i = p0 + threadIdx.x; i < p1; i += kBlock) {
-            uint64_t k = s.live_key[g.v_edges[i]];
+            uint64_t k = vertex_key(g, s, round, seed, g.v_edges[i]);
             mx = k > mx ? k : mx;
         }
 #pragma unroll
@@ -373,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int rou
             uint64_t k = 0;
             if (t < total) {
                 j = find_item(L.start, t);
-                k = s.live_key[g.v_edges[L.base[j] + (t - L.start[j])]];
+                k = vertex_key(g, s, round, seed, g.v_edges[L.base[j] + (t - L.start[j])]);
             }
             // segmented inclusive max-scan over the wave, segments = equal j
 #pragma unroll
@@ -392,105 +474,149 @@ __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int rou
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, uint32_t seed) {
+    __shared__ ChunkLds L;
+    vertex_max_body(g, s, L, round, seed);
+}
+
+// Round-0 maximum when the library chooses the form (AUTO).  The edge-centric
+// scatter pays one L2-cached read per incidence and an atomic only where the
+// key raises the maximum, so it is fastest when most incidences fall on a few
+// hot vertices whose entries stay in L2; the vertex-centric pass gathers one
+// weight per incidence with no atomics, which is faster when incidences are
+// spread evenly.  k_init counted the incidences of vertices of degree >=
+// kHotDegree; the edge form is taken when they are at least half of all.
+__global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed) {
+    __shared__ ChunkLds L;
+    __shared__ int edge_form;
+    if (threadIdx.x < kWave) {
+        unsigned long long hot = s.hot[threadIdx.x];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) hot += __shfl_xor(hot, o, kWave);
+        if (threadIdx.x == 0) {
+            edge_form = 2 * hot >= (unsigned long long)g.kappa;
+            if (blockIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
+        }
+    }
+    __syncthreads();
+    if (edge_form) {
+        if ((int)blockIdx.x < s.grid) scatter0_region(g, s, L, blockIdx.x);
+    } else {
+        vertex_max_body(g, s, L, 0, seed);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Local-max test of round r (Algorithm 1 third phase; Algorithm 2 P_e = |e|):
 // a live edge is matched iff best[v] == key(e) at every pin v.  Matched edges
 // set their bitmap bit and mark their pins done (exclusive: a vertex has one
-// maximum edge).  With clear_next the pass also zeroes best[(r+1) & 1] at
-// every pin it reads; the next round's survivors are a subset of this
-// round's live edges, so the next scatter starts from zero at all its pins.
-// The first thread also clears the counters of round r+1.
+// maximum edge).
+// With clear_next the next round's buffer best[(r+1) & 1] is zeroed: by one
+// streaming pass over all n entries when the round has many pins (kappa_r >=
+// n / 8: a full sequential clear is cheaper than as many scattered stores),
+// else at every pin this pass reads.  The next round's survivors are a subset
+// of this round's live edges, so the next scatter starts from zero at all of
+// its pins.  Workgroup 0 also clears the counters of round r+1.
+constexpr int kFullClearRatio = 8;
+
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, int clear_next,
                                                  uint32_t *bits) {
     __shared__ ChunkLds L;
-    RoundSlot *slot = &s.slots[round % s.ring];
-    const int32_t *list = round == 0 ? nullptr : s.list[round & 1];
+    __shared__ int full_clear;
+    const int b = blockIdx.x;
+    const int cnt = region_count(s, g.m, round, b);
     const uint64_t *best = s.best[round & 1];
     uint64_t *next = s.best[(round + 1) & 1];
-    const int cnt = slot->live;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        RoundSlot z = {0, 0, 0, 0, 0};
-        s.slots[(round + 1) % s.ring] = z;
+    RoundStats *st_cur = &s.stats[round % s.ring];
+    if (b == 0) {
+        unsigned long long *z = (unsigned long long *)&s.stats[(round + 1) % s.ring];
+        for (int i = threadIdx.x; i < (int)(sizeof(RoundStats) / 8); i += kBlock) z[i] = 0;
     }
-    for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < cnt; c0 += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)c0 + threadIdx.x;
+    if (clear_next) {
+        if (threadIdx.x < kWave) {
+            unsigned long long k = st_cur->kappa[threadIdx.x];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) k += __shfl_xor(k, o, kWave);
+            if (threadIdx.x == 0) full_clear = k * kFullClearRatio >= (unsigned long long)g.n;
+        }
+        __syncthreads();
+        if (full_clear) {
+            const int64_t stride = (int64_t)gridDim.x * kBlock;
+            for (int64_t v = (int64_t)b * kBlock + threadIdx.x; v < g.n; v += stride) next[v] = 0;
+        }
+    }
+    const bool clear_pins = clear_next && !full_clear;
+    unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
+    for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+        const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
         if (i < cnt) {
-            e = list ? list[i] : i;
+            e = region_item(s, round, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
             key = s.key[e];
         }
-        int total;
-        int st = block_exclusive_sum(len, L.wave_tmp, &total);
-        L.start[threadIdx.x] = st;
-        L.base[threadIdx.x] = base;
-        L.key[threadIdx.x] = key;
-        L.flag[threadIdx.x] = 0;
-        __syncthreads();
-        for (int t = threadIdx.x; t < total; t += kBlock) {
-            int j = find_item(L.start, t);
-            int pin = g.e_pins[L.base[j] + (t - L.start[j])];
-            if (best[pin] != L.key[j]) L.flag[j] = 1;
-            if (clear_next) next[pin] = 0;
+        int matched;
+        if (!clear_pins) {
+            // One lane per edge, stopping at the first pin where the edge is
+            // not the maximum: almost every edge fails at its first pin.
+            // The first pin alone, then the rest kUnroll at a time.
+            bool ok = e >= 0 && (len == 0 || best[g.e_pins[base]] == key);
+            for (int k0 = 1; k0 < len && ok; k0 += kUnroll) {
+                int p[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] : -1;
+                uint64_t bv[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) bv[u] = p[u] >= 0 ? best[p[u]] : key;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) ok = ok && bv[u] == key;
+            }
+            matched = ok ? 1 : 0;
+        } else {
+            // Every pin is visited (its next-round entry is cleared), spread
+            // over the lanes.
+            int total;
+            int st = block_exclusive_sum(len, L.wave_tmp, &total);
+            L.start[threadIdx.x] = st;
+            L.base[threadIdx.x] = base;
+            L.key[threadIdx.x] = key;
+            L.flag[threadIdx.x] = 0;
+            __syncthreads();
+            for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
+                int j[kUnroll], pin[kUnroll];
+                chunk_pins(L, g.e_pins, total, t0, j, pin);
+                uint64_t bv[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) bv[u] = j[u] >= 0 ? best[pin[u]] : 0;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (j[u] < 0) continue;
+                    if (bv[u] != L.key[j[u]]) L.flag[j[u]] = 1;
+                    next[pin[u]] = 0;
+                }
+            }
+            __syncthreads();
+            matched = (e >= 0 && !L.flag[threadIdx.x]) ? 1 : 0;
+            __syncthreads();
         }
-        __syncthreads();
-        const int matched = (e >= 0 && !L.flag[threadIdx.x]) ? 1 : 0;
-        if (matched) atomicOr(&bits[e >> 5], 1u << (e & 31));
-        unsigned long long nm = block_sum_u64(matched, L.sum_tmp);
-        unsigned long long wm = block_sum_u64(matched ? (unsigned long long)(key >> 32) : 0ull,
-                                              L.sum_tmp);
-        if (threadIdx.x == 0 && nm) {
-            atomicAdd((unsigned long long *)&slot->matched, nm);
-            atomicAdd((unsigned long long *)&slot->weight, wm);
+        if (matched) {
+            atomicOr(&bits[e >> 5], 1u << (e & 31));
+            nm += 1;
+            wm += key >> 32;
+            pm += (unsigned long long)len;
+            for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k]] = 1;
         }
-        int total2;
-        int st2 = block_exclusive_sum(matched ? len : 0, L.wave_tmp, &total2);
-        L.start[threadIdx.x] = st2;
-        __syncthreads();
-        for (int t = threadIdx.x; t < total2; t += kBlock) {
-            int j = find_item(L.start, t);
-            s.done[g.e_pins[L.base[j] + (t - L.start[j])]] = 1;
-        }
-        __syncthreads();
     }
-}
-
-// Builds the list of split (hub) vertices for the vertex-centric pass.
-__global__ void __launch_bounds__(kBlock) k_find_hubs(Graph g, State s, int hub_threshold) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-        if (g.v_off[v + 1] - g.v_off[v] > hub_threshold) {
-            int idx = atomicAdd(s.hub_count, 1);
-            s.hubs[idx] = (int32_t)v;
-        }
+    nm = block_sum_u64(nm, L.sum_tmp);
+    wm = block_sum_u64(wm, L.sum_tmp);
+    pm = block_sum_u64(pm, L.sum_tmp);
+    if (threadIdx.x == 0 && nm) {
+        atomicAdd(&st_cur->matched[b % kSub], nm);
+        atomicAdd(&st_cur->weight[b % kSub], wm);
+        atomicAdd(&st_cur->mpins[b % kSub], pm);
     }
-}
-
-// Piece offsets of the hubs (one workgroup): hub_piece_off[h] = number of
-// kHubPiece pieces of hubs 0..h-1.
-__global__ void __launch_bounds__(kBlock) k_hub_pieces(Graph g, State s) {
-    __shared__ int wave_tmp[kWaves];
-    __shared__ int carry;
-    const int nh = *s.hub_count;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int h0 = 0; h0 < nh; h0 += kBlock) {
-        const int h = h0 + threadIdx.x;
-        int np = 0;
-        if (h < nh) {
-            const int v = s.hubs[h];
-            np = (g.v_off[v + 1] - g.v_off[v] + kHubPiece - 1) / kHubPiece;
-        }
-        int total;
-        int ex = block_exclusive_sum(np, wave_tmp, &total);
-        if (h < nh) s.hub_piece_off[h] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) s.hub_piece_off[nh] = carry;
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero_words(uint32_t *p, int64_t n) {
@@ -501,8 +627,10 @@ __global__ void __launch_bounds__(kBlock) k_zero_words(uint32_t *p, int64_t n) {
 }  // namespace
 
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
-                       uint32_t *bits, int crew) {
-    hipLaunchKernelGGL(k_init, dim3(L.grid), dim3(kBlock), 0, L.stream, g, seed, s, bits, crew);
+                       uint32_t *bits, int init_flags) {
+    hipLaunchKernelGGL(k_prologue, dim3(1), dim3(kBlock), 0, L.stream, g, s);
+    hipLaunchKernelGGL(k_init, dim3(L.grid), dim3(kBlock), 0, L.stream, g, seed, s, bits,
+                       init_flags);
     return hipGetLastError();
 }
 
@@ -514,34 +642,31 @@ hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, int round) {
-    (void)round;
-    hipLaunchKernelGGL(k_scatter0, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s);
+hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s) {
+    hipLaunchKernelGGL(k_scatter0, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s);
     return hipGetLastError();
 }
 
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter) {
-    hipLaunchKernelGGL(k_retire, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, round, scatter);
+    hipLaunchKernelGGL(k_retire, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, scatter);
+    return hipGetLastError();
+}
+
+hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed) {
+    const int grid = L.grid > s.grid ? L.grid : s.grid;
+    hipLaunchKernelGGL(k_max0, dim3(grid), dim3(kBlock), 0, L.stream, g, s, seed);
     return hipGetLastError();
 }
 
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
-                             int hub_threshold) {
-    if (round == 0) {
-        hipLaunchKernelGGL(k_find_hubs, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s,
-                           hub_threshold);
-        hipLaunchKernelGGL(k_hub_pieces, dim3(1), dim3(kBlock), 0, L.stream, g, s);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_vertex_max, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, round,
-                       hub_threshold);
+                             uint32_t seed) {
+    hipLaunchKernelGGL(k_vertex_max, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, round, seed);
     return hipGetLastError();
 }
 
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
                        uint32_t *bits) {
-    hipLaunchKernelGGL(k_test, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, round, clear_next,
+    hipLaunchKernelGGL(k_test, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, clear_next,
                        bits);
     return hipGetLastError();
 }

@@ -87,7 +87,7 @@ def test_match_rejects_bad_arguments_without_gpu(lib):
     assert hgm.hgm_match(c, 1, bits, ws, 1 << 30, hgm.make_opts("crew")) == hgm.HGM_E_ARG
     assert lib.hgm_match(None, 1, None, None, 0, None, None, None) == hgm.HGM_E_ARG
     st = hgm.HgmStats()
-    st.cap = 4
+    st.cap = -1
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, None, 0, st) == hgm.HGM_E_ARG
     o = hgm.make_opts(rounds_per_sync=1000)
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
