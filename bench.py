@@ -59,8 +59,10 @@ def algorithmic_bytes(stats, variant_rounds, n):
       retire: per edge id 4 (not in round 0) + offsets 8, per pin pin 4 +
               done 1, per survivor id write 4 (+ key 8 and 8 per surviving
               pin for the fused CRCW scatter; CREW: 8 per dead edge key)
-      vertex max (CREW): per vertex done 1 + offsets 4 + best 8, per pin of
-              a vertex still open v_edges 4 + key 8 (counted over all pins)
+      vertex max: per vertex done 1 + offsets 4 + best 8, per pin v_edges 4
+              + weight 4 in round 0 (the key is rebuilt from the weight) or
+              live key 8 in later rounds of the CREW variant (these scan every
+              open vertex's whole list; counted over all pins, an upper bound)
     """
     E = list(stats["live_edges"]) + [0]
     K = list(stats["live_pins"]) + [0]
@@ -75,7 +77,7 @@ def algorithmic_bytes(stats, variant_rounds, n):
         if r == 0 and not crew_r:
             out["scatter"] += 12 * E[0] + 12 * K[0]
         if crew_r:
-            out["vertex_max"] += 13 * n + 12 * K[0]
+            out["vertex_max"] += 13 * n + (8 if r == 0 else 12) * K[0]
         out["test"] += (idb + 16) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
         ret = (idb + 8) * E[r] + 5 * K[r] + 4 * E[r + 1]
         if crew_next:
@@ -86,7 +88,12 @@ def algorithmic_bytes(stats, variant_rounds, n):
     return out
 
 
-def load_traffic(workload, kernel, digest):
+def load_traffic(workload, kernel, digest, launches):
+    """HBM bytes per launch of `kernel` from the committed PMC summary.
+
+    The summary holds calibrated FETCH_SIZE + WRITE_SIZE bytes per call
+    (summed over the class's dispatches); per launch is that over this run's
+    launch count, as for `achieved`.  None when the kernels changed since."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -98,7 +105,9 @@ def load_traffic(workload, kernel, digest):
                     if d.get("kernel_source") != digest:
                         return None
                     k = d.get("kernels", {}).get(kernel)
-                    return None if k is None else k.get("bytes_per_launch")
+                    if k is None or not launches:
+                        return None
+                    return k.get("bytes_per_call") / launches
     except (OSError, ValueError):
         return None
     return None
@@ -219,14 +228,15 @@ def main():
     t_step_events = (time.perf_counter() - t1) / args.steps
 
     crew_all = args.variant == "crew"
-    model = algorithmic_bytes(st, lambda r: crew_all, g.n)
+    crew0 = crew_all or launches.get("vertex_max", 0) > 0   # AUTO's round-0 form
+    model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n)
     cand = {k: tot_ms[k] for k in model if tot_ms.get(k, 0) > 0}
     dom = max(cand, key=cand.get)
     dom_ms = tot_ms[dom] / args.steps
     dom_launch = launches[dom] / args.steps
     achieved = model[dom] / (dom_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    traffic = load_traffic(args.workload, dom, digest)
+    traffic = load_traffic(args.workload, dom, digest, dom_launch)
 
     result = {
         "metric": METRIC,

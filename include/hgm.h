@@ -138,6 +138,54 @@ size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts);
 int hgm_match(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits, void *workspace,
               size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats);
 
+/* A batch of independent hypergraphs matched in one call.  Instances keep
+ * their own (local) ids, so instance i's slices are byte-identical to its
+ * standalone hgm_csr; all arrays are the instances' arrays concatenated in
+ * order.  Base arrays have count + 1 entries (prefix sums, [0] = 0):
+ *   v_base[i]    first vertex of instance i   (v_base[count] = n_total)
+ *   e_base[i]    first edge                   (e_base[count] = m_total)
+ *   pin_base[i]  first incidence              (pin_base[count] = kappa_total)
+ *   word_base[i] first bitmap word            (word_base[count] = words_total)
+ *   e_off        int32[m_total + count]: instance i's m_i + 1 local offsets
+ *                start at e_off[e_base[i] + i]
+ *   e_pins       int32[kappa_total] local vertex ids
+ *   v_off        int32[n_total + count]: instance i's n_i + 1 local offsets
+ *                start at v_off[v_base[i] + i] (may be NULL, as in hgm_csr)
+ *   v_edges      int32[kappa_total] local edge ids (may be NULL)
+ *   w            uint32[m_total]
+ *   seeds        uint32[count] priority-hash seed of each instance
+ * All pointers are device pointers.  Instance i's matching is written to
+ * words word_base[i] .. word_base[i] + ceil(m_i / 32) of the output bitmap
+ * (edge e at bit e % 32 of word word_base[i] + e / 32) and equals what
+ * hgm_match returns for that instance and seed alone.  Limits: n_total,
+ * m_total, kappa_total and 32 * words_total below 2^31. */
+typedef struct hgm_batch {
+    int32_t count;
+    int64_t n_total, m_total, kappa_total, words_total;
+    const int64_t *v_base;
+    const int64_t *e_base;
+    const int64_t *pin_base;
+    const int64_t *word_base;
+    const int32_t *e_off;
+    const int32_t *e_pins;
+    const int32_t *v_off;
+    const int32_t *v_edges;
+    const uint32_t *w;
+    const uint32_t *seeds;
+} hgm_batch;
+
+/* Workspace bytes for hgm_match_batch (0 on invalid sizes or options). */
+size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts);
+
+/* Match every instance of a batch in one pass of launches: the instances are
+ * vertex-disjoint, so the local-max rounds of their union select each
+ * instance's own matching; each instance leaves the live set when its last
+ * live edge is gone, and the call ends when all have.  Options and stats as
+ * for hgm_match (stats aggregate over the batch); opts->validate is not
+ * supported here (HGM_E_ARG): validate instances with hgm_match. */
+int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace, size_t ws_bytes,
+                    const hgm_opts *opts, void *stream, hgm_stats *stats);
+
 /* Short English description of an HGM_* code (static storage). */
 const char *hgm_strerror(int code);
 

@@ -25,7 +25,8 @@ HGM_VARIANT_CRCW = 1
 HGM_VARIANT_CREW = 2
 VARIANTS = {"auto": HGM_VARIANT_AUTO, "crcw": HGM_VARIANT_CRCW, "crew": HGM_VARIANT_CREW}
 
-EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_strerror", "hgm_version"]
+EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_batch_workspace_size", "hgm_match_batch",
+            "hgm_strerror", "hgm_version"]
 
 
 class HgmCsr(ctypes.Structure):
@@ -39,6 +40,16 @@ class HgmOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32)]
+
+
+class HgmBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n_total", ctypes.c_int64), ("m_total", ctypes.c_int64),
+                ("kappa_total", ctypes.c_int64), ("words_total", ctypes.c_int64),
+                ("v_base", ctypes.c_void_p), ("e_base", ctypes.c_void_p),
+                ("pin_base", ctypes.c_void_p), ("word_base", ctypes.c_void_p),
+                ("e_off", ctypes.c_void_p), ("e_pins", ctypes.c_void_p),
+                ("v_off", ctypes.c_void_p), ("v_edges", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("seeds", ctypes.c_void_p)]
 
 
 HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE = range(5)
@@ -80,6 +91,11 @@ def load():
     lib.hgm_match.restype = ctypes.c_int
     lib.hgm_match.argtypes = [ctypes.POINTER(HgmCsr), ctypes.c_uint32, P, P, ctypes.c_size_t,
                               ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
+    lib.hgm_batch_workspace_size.restype = ctypes.c_size_t
+    lib.hgm_batch_workspace_size.argtypes = [ctypes.POINTER(HgmBatch), ctypes.POINTER(HgmOpts)]
+    lib.hgm_match_batch.restype = ctypes.c_int
+    lib.hgm_match_batch.argtypes = [ctypes.POINTER(HgmBatch), P, P, ctypes.c_size_t,
+                                    ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
     lib.hgm_strerror.restype = ctypes.c_char_p
     lib.hgm_strerror.argtypes = [ctypes.c_int]
     lib.hgm_version.restype = ctypes.c_int
@@ -110,6 +126,21 @@ def hgm_match(csr: HgmCsr, seed: int, bits_ptr: int, ws_ptr: int, ws_bytes: int,
                                 ctypes.byref(opts) if opts is not None else None,
                                 stream or None,
                                 ctypes.byref(stats) if stats is not None else None))
+
+
+def hgm_batch_workspace_size(batch: HgmBatch, opts: HgmOpts | None = None) -> int:
+    return int(load().hgm_batch_workspace_size(ctypes.byref(batch),
+                                               ctypes.byref(opts) if opts is not None else None))
+
+
+def hgm_match_batch(batch: HgmBatch, bits_ptr: int, ws_ptr: int, ws_bytes: int,
+                    opts: HgmOpts | None = None, stream: int = 0,
+                    stats: HgmStats | None = None) -> int:
+    """Raw call; returns the HGM_* code."""
+    return int(load().hgm_match_batch(ctypes.byref(batch), bits_ptr or None, ws_ptr or None,
+                                      ws_bytes, ctypes.byref(opts) if opts is not None else None,
+                                      stream or None,
+                                      ctypes.byref(stats) if stats is not None else None))
 
 
 # ---------------------------------------------------------------------------
@@ -151,6 +182,50 @@ class DeviceHypergraph:
         return c
 
 
+class DeviceBatch:
+    """Concatenated instances (instance-local ids) resident on a GPU."""
+
+    def __init__(self, count, n_total, m_total, kappa_total, words_total, v_base, e_base,
+                 pin_base, word_base, e_off, e_pins, v_off, v_edges, w, seeds):
+        self.count = int(count)
+        self.n_total, self.m_total = int(n_total), int(m_total)
+        self.kappa_total, self.words_total = int(kappa_total), int(words_total)
+        self.v_base, self.e_base, self.pin_base, self.word_base = v_base, e_base, pin_base, word_base
+        self.e_off, self.e_pins, self.v_off, self.v_edges, self.w, self.seeds = (
+            e_off, e_pins, v_off, v_edges, w, seeds)
+
+    @classmethod
+    def from_host(cls, b, device="cuda"):
+        """Copy a host batch (synth.Batch-like numpy arrays) to `device`."""
+        torch = _torch()
+        import numpy as np
+
+        def t(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a).astype(dt, copy=False)).to(device)
+
+        return cls(b.count, int(b.v_base[-1]), int(b.e_base[-1]), int(b.pin_base[-1]),
+                   int(b.word_base[-1]), t(b.v_base, np.int64), t(b.e_base, np.int64),
+                   t(b.pin_base, np.int64), t(b.word_base, np.int64), t(b.e_off, np.int32),
+                   t(b.e_pins, np.int32), t(b.v_off, np.int32), t(b.v_edges, np.int32),
+                   t(np.asarray(b.w, dtype=np.uint32).view(np.int32), np.int32),
+                   t(np.asarray(b.seeds, dtype=np.uint32).view(np.int32), np.int32))
+
+    def c_struct(self) -> HgmBatch:
+        c = HgmBatch()
+        c.count, c.n_total, c.m_total = self.count, self.n_total, self.m_total
+        c.kappa_total, c.words_total = self.kappa_total, self.words_total
+
+        def p(x):
+            return x.data_ptr() if x is not None and x.numel() else None
+
+        c.v_base, c.e_base, c.pin_base, c.word_base = (p(self.v_base), p(self.e_base),
+                                                       p(self.pin_base), p(self.word_base))
+        c.e_off, c.e_pins, c.v_off, c.v_edges = (p(self.e_off), p(self.e_pins), p(self.v_off),
+                                                 p(self.v_edges))
+        c.w, c.seeds = p(self.w), p(self.seeds)
+        return c
+
+
 def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False,
               max_rounds=0) -> HgmOpts:
     o = HgmOpts()
@@ -160,6 +235,63 @@ def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False
     o.validate = 1 if validate else 0
     o.max_rounds = max_rounds
     return o
+
+
+def alloc_batch_workspace(db: DeviceBatch, opts: HgmOpts | None = None):
+    torch = _torch()
+    nbytes = hgm_batch_workspace_size(db.c_struct(), opts)
+    if nbytes == 0:
+        raise HgmError(HGM_E_ARG, "hgm_batch_workspace_size")
+    return torch.empty(nbytes, dtype=torch.uint8, device=db.e_pins.device)
+
+
+def _stats_struct(cap, timing):
+    import numpy as np
+    arrays = [np.zeros(max(cap, 1), dtype=np.int64) for _ in range(4)]
+    rms = np.zeros(max(cap, 1), dtype=np.float32)
+    st = HgmStats()
+    st.cap = cap
+    st.live_edges, st.live_pins, st.matched_per_round, st.matched_pins = [
+        a.ctypes.data_as(ctypes.c_void_p) for a in arrays]
+    st.timing = 1 if timing else 0
+    st.round_ms = rms.ctypes.data_as(ctypes.c_void_p)
+    return st, arrays, rms
+
+
+def _stats_dict(st, arrays, rms, timing):
+    r = st.rounds
+    k = min(r, st.cap)
+    d = {"rounds": r, "matched": st.matched, "weight": st.weight,
+         "live_edges": arrays[0][:k].copy(), "live_pins": arrays[1][:k].copy(),
+         "matched_per_round": arrays[2][:k].copy(), "matched_pins": arrays[3][:k].copy()}
+    if timing:
+        d["round_ms"] = rms[:k].copy()
+        d["kernel_ms"] = {KERNEL_CLASS_NAMES[c]: st.kernel_ms[c] for c in range(HGM_K_CLASSES)}
+        d["kernel_launches"] = {KERNEL_CLASS_NAMES[c]: st.kernel_launches[c]
+                                for c in range(HGM_K_CLASSES)}
+    return d
+
+
+def match_batch(db: DeviceBatch, opts: HgmOpts | None = None, workspace=None, bits=None,
+                stream=None, want_stats=True, cap=None, timing=False):
+    """Run hgm_match_batch; returns (bits int32 tensor [words_total], stats or None)."""
+    torch = _torch()
+    dev = db.e_pins.device
+    if workspace is None:
+        workspace = alloc_batch_workspace(db, opts)
+    if bits is None:
+        bits = torch.empty(max(db.words_total, 1), dtype=torch.int32, device=dev)
+    st = arrays = rms = None
+    if want_stats or timing:
+        st, arrays, rms = _stats_struct(min(db.m_total + 1, 1 << 16) if cap is None else cap,
+                                        timing)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = hgm_match_batch(db.c_struct(), bits.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                         opts, stream, st)
+    if rc != HGM_OK:
+        raise HgmError(rc, "hgm_match_batch")
+    return bits[:db.words_total], (_stats_dict(st, arrays, rms, timing) if st is not None else None)
 
 
 def alloc_workspace(dg: DeviceHypergraph, opts: HgmOpts | None = None):
@@ -181,35 +313,13 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
     words = (dg.m + 31) // 32
     if bits is None:
         bits = torch.empty(max(words, 1), dtype=torch.int32, device=dev)
-    st = None
-    arrays = None
+    st = arrays = rms = None
     if want_stats or timing:
-        cap = min(dg.m + 1, 1 << 16) if cap is None else cap
-        arrays = [np.zeros(max(cap, 1), dtype=np.int64) for _ in range(4)]
-        rms = np.zeros(max(cap, 1), dtype=np.float32)
-        st = HgmStats()
-        st.cap = cap
-        st.live_edges, st.live_pins, st.matched_per_round, st.matched_pins = [
-            a.ctypes.data_as(ctypes.c_void_p) for a in arrays]
-        st.timing = 1 if timing else 0
-        st.round_ms = rms.ctypes.data_as(ctypes.c_void_p)
+        st, arrays, rms = _stats_struct(min(dg.m + 1, 1 << 16) if cap is None else cap, timing)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     rc = hgm_match(dg.csr(), seed, bits.data_ptr(), workspace.data_ptr(), workspace.numel(),
                    opts, stream, st)
     if rc != HGM_OK:
         raise HgmError(rc, "hgm_match")
-    stats = None
-    if st is not None:
-        r = st.rounds
-        k = min(r, st.cap)
-        stats = {"rounds": r, "matched": st.matched, "weight": st.weight,
-                 "live_edges": arrays[0][:k].copy(), "live_pins": arrays[1][:k].copy(),
-                 "matched_per_round": arrays[2][:k].copy(),
-                 "matched_pins": arrays[3][:k].copy()}
-        if timing:
-            stats["round_ms"] = rms[:k].copy()
-            stats["kernel_ms"] = {KERNEL_CLASS_NAMES[c]: st.kernel_ms[c] for c in range(HGM_K_CLASSES)}
-            stats["kernel_launches"] = {KERNEL_CLASS_NAMES[c]: st.kernel_launches[c]
-                                        for c in range(HGM_K_CLASSES)}
-    return bits[:words], stats
+    return bits[:words], (_stats_dict(st, arrays, rms, timing) if st is not None else None)

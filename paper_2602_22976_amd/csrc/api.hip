@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "hgm.h"
@@ -13,7 +14,8 @@ using namespace hgm;
 
 namespace {
 
-constexpr int kDefaultRoundsPerSync = 4;
+constexpr int kFirstBatch = 4;         // rounds enqueued before the first termination check
+constexpr int kAdaptiveMaxBatch = 32;  // cap of a predicted batch
 constexpr int kMaxRoundsPerSync = 200;
 constexpr int kDefaultHubThreshold = 8192;
 constexpr int kBlocksPerCu = 8;
@@ -23,7 +25,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, pieces,
-        piece_count, hot, vbits, total;
+        piece_count, hot, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
 };
 
@@ -38,6 +40,7 @@ void edge_schedule(int64_t m, int *grid, int *region) {
 
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
+    bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
     bool have_vertex_side;  // v_off / v_edges given
 };
 
@@ -50,7 +53,8 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     if (d.rounds_per_sync > kMaxRoundsPerSync) return HGM_E_ARG;
     o->variant = d.variant;
     o->hub_threshold = d.hub_threshold ? d.hub_threshold : kDefaultHubThreshold;
-    o->rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : kDefaultRoundsPerSync;
+    o->adaptive = d.rounds_per_sync == 0;
+    o->rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : kAdaptiveMaxBatch;
     o->validate = d.validate != 0;
     o->max_rounds = d.max_rounds;
     return HGM_OK;
@@ -69,7 +73,7 @@ bool crew_round(const Opts &o, int r) {
 bool any_crew_round(const Opts &o) { return crew_round(o, 0); }
 bool uses_live_key(const Opts &o) { return o.variant == HGM_VARIANT_CREW; }
 
-Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o) {
+Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batch = false) {
     Layout L;
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -101,6 +105,12 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o) {
     L.piece_count = take(4);
     L.hot = take(8 * (size_t)kSub);
     L.vbits = take(o.validate ? 4 * (size_t)((kappa + 31) / 32) : 0);
+    // Batch: global offsets and per-edge / per-vertex bases (see Graph).
+    L.goff = take(batch ? 4 * ((size_t)m + 1) : 0);
+    L.vbase = take(batch ? 4 * (size_t)m : 0);
+    L.bitoff = take(batch ? 4 * (size_t)m : 0);
+    L.gvoff = take(batch && o.have_vertex_side ? 4 * ((size_t)n + 1) : 0);
+    L.ebase = take(batch && o.have_vertex_side ? 4 * (size_t)n : 0);
     L.total = at;
     return L;
 }
@@ -131,8 +141,54 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     return s;
 }
 
+// Rounds to enqueue before the next termination check.  Live pins shrink by a
+// factor per round that grows as the instance thins out, so with the latest
+// factor f the rounds left are at most about log(kappa_r) / log(f); a little
+// over half of that, plus the retire pass that finds the live set empty,
+// matched the measured round counts.  An unneeded round costs two
+// near-empty launches (a few microseconds each), a missing one a further host
+// round trip (tens of microseconds).
+int next_batch(const Opts &o, int launched, const std::vector<int64_t> &live_pins) {
+    if (!o.adaptive) return o.rounds_per_sync;
+    if (launched == 0 || live_pins.size() < 2) return kFirstBatch;
+    const double cur = (double)live_pins.back();
+    const double prev = (double)live_pins[live_pins.size() - 2];
+    if (cur <= 1.0) return 2;
+    double ratio = prev > cur ? prev / cur : 1.0;
+    if (ratio < 1.5) ratio = 1.5;
+    const int left = (int)std::ceil(0.55 * std::log(cur) / std::log(ratio)) + 1;
+    return std::max(2, std::min(kAdaptiveMaxBatch, left));
+}
+
 void bind_graph(Opts *o, const hgm_csr *g) {
     o->have_vertex_side = g && g->v_off && (g->kappa == 0 || (g->v_edges && g->n > 0));
+}
+
+int check_batch(const hgm_batch *b, const Opts &o) {
+    if (!b) return HGM_E_ARG;
+    if (b->count < 0 || b->n_total < 0 || b->m_total < 0 || b->kappa_total < 0 ||
+        b->words_total < 0)
+        return HGM_E_ARG;
+    const int64_t lim = ((int64_t)1 << 31) - 1;
+    if (b->n_total > lim || b->m_total > lim || b->kappa_total > lim ||
+        32 * b->words_total > lim)
+        return HGM_E_SIZE;
+    if (b->count > 0 && (!b->v_base || !b->e_base || !b->pin_base || !b->word_base || !b->seeds))
+        return HGM_E_ARG;
+    if (b->m_total > 0 && (!b->e_off || !b->w)) return HGM_E_ARG;
+    if (b->kappa_total > 0 && (!b->e_pins || b->m_total == 0)) return HGM_E_ARG;
+    if (b->m_total > 0 && b->count == 0) return HGM_E_ARG;
+    if (o.variant == HGM_VARIANT_CREW) {
+        if (!b->v_off) return HGM_E_ARG;
+        if (b->kappa_total > 0 && (!b->v_edges || b->n_total == 0)) return HGM_E_ARG;
+    }
+    if (o.validate) return HGM_E_ARG;  // validate each instance with hgm_match instead
+    return HGM_OK;
+}
+
+void bind_batch(Opts *o, const hgm_batch *b) {
+    o->have_vertex_side =
+        b && b->v_off && (b->kappa_total == 0 || (b->v_edges && b->n_total > 0));
 }
 
 int check_graph(const hgm_csr *g, const Opts &o) {
@@ -238,63 +294,11 @@ struct KernelTimer {
         if ((expr) != hipSuccess) return HGM_E_HIP;     \
     } while (0)
 
-}  // namespace
-
-extern "C" {
-
-int hgm_version(void) { return 100; }
-
-const char *hgm_strerror(int code) {
-    switch (code) {
-    case HGM_OK: return "success";
-    case HGM_E_ARG: return "invalid argument (NULL pointer with non-zero size, negative size or bad option)";
-    case HGM_E_CSR: return "malformed hypergraph (offsets, ids, repeated pins or vertex side not the transpose)";
-    case HGM_E_SIZE: return "size limit: kappa >= 2^31 or workspace too small";
-    case HGM_E_ROUND_LIMIT: return "round limit reached with live edges remaining";
-    case HGM_E_HIP: return "HIP runtime error";
-    default: return "unknown error code";
-    }
-}
-
-size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts) {
-    Opts o;
-    if (resolve_opts(opts, &o) != HGM_OK || !g) return 0;
-    bind_graph(&o, g);
-    if (g->n < 0 || g->m < 0 || g->kappa < 0 || g->kappa >= ((int64_t)1 << 31)) return 0;
-    return make_layout(g->n, g->m, g->kappa, o).total;
-}
-
-int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *workspace,
-              size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats) {
-    Opts o;
-    int rc = resolve_opts(opts, &o);
-    if (rc != HGM_OK) return rc;
-    rc = check_graph(gin, o);
-    if (rc != HGM_OK) return rc;
-    bind_graph(&o, gin);
-    if (gin->m > 0 && !matched_bits) return HGM_E_ARG;
-    if (stats && stats->cap < 0) return HGM_E_ARG;
-    const Layout lay = make_layout(gin->n, gin->m, gin->kappa, o);
-    if (!workspace) return HGM_E_ARG;
-    if (ws_bytes < lay.total) return HGM_E_SIZE;
-    if (((uintptr_t)workspace & 255) != 0) return HGM_E_ARG;
-
-    Graph g;
-    g.n = gin->n;
-    g.m = gin->m;
-    g.kappa = gin->kappa;
-    g.e_off = gin->e_off;
-    g.e_pins = gin->e_pins;
-    g.v_off = gin->v_off;
-    g.v_edges = gin->v_edges;
-    g.w = gin->w;
-    const State s = carve(workspace, lay, o);
-    Launch L;
-    L.grid = device_grid();
-    L.stream = (hipStream_t)stream;
-    if (L.grid <= 0) return HGM_E_HIP;
-
-    int init_flags = 0;
+// Enqueues setup and rounds, checking termination on the host every batch of
+// rounds; shared by the single-instance and the batched entry point.
+int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s, const Launch &L,
+               uint32_t seed, uint32_t *matched_bits, hgm_stats *stats, const BatchIn *batch) {
+    int init_flags = batch ? kInitKeysDone : 0;
     if (uses_live_key(o)) init_flags |= kInitLiveKey;
     if (any_crew_round(o)) init_flags |= kInitHubs;
     KernelTimer T;
@@ -309,6 +313,7 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     std::vector<float> round_ms;
     constexpr int kSetup = -1;
     HGM_TRY(T.start());
+    if (batch) HGM_TRY(launch_batch_setup(L, g, *batch, s));
     HGM_TRY(launch_init(L, g, seed, s, matched_bits, init_flags));
     HGM_TRY(T.after(HGM_K_SETUP, kSetup));
     if (o.validate) {
@@ -345,7 +350,7 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     }
     int launched = 0;  // rounds whose test has been enqueued
     while (!finished) {
-        int batch = o.rounds_per_sync;
+        int batch = next_batch(o, launched, live_p);
         if (o.max_rounds > 0) batch = std::min(batch, o.max_rounds - launched);
         if (batch <= 0) return HGM_E_ROUND_LIMIT;
         const int first = launched;
@@ -364,8 +369,14 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
             }
             launched += 1;
         }
-        HGM_TRY(hipMemcpyAsync(ring.data(), s.stats, sizeof(RoundStats) * lay.ring,
-                               hipMemcpyDeviceToHost, L.stream));
+        // Copy the slots of rounds first .. launched (at most two ranges of the ring).
+        for (int r = first; r <= launched;) {
+            const int slot = r % lay.ring;
+            const int run = std::min(launched - r + 1, lay.ring - slot);
+            HGM_TRY(hipMemcpyAsync(&ring[slot], &s.stats[slot], sizeof(RoundStats) * run,
+                                   hipMemcpyDeviceToHost, L.stream));
+            r += run;
+        }
         HGM_TRY(hipStreamSynchronize(L.stream));
         auto sum = [](const unsigned long long *a) {
             unsigned long long t = 0;
@@ -414,6 +425,127 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
         stats->weight = tw;
     }
     return HGM_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int hgm_version(void) { return 100; }
+
+const char *hgm_strerror(int code) {
+    switch (code) {
+    case HGM_OK: return "success";
+    case HGM_E_ARG: return "invalid argument (NULL pointer with non-zero size, negative size or bad option)";
+    case HGM_E_CSR: return "malformed hypergraph (offsets, ids, repeated pins or vertex side not the transpose)";
+    case HGM_E_SIZE: return "size limit: kappa >= 2^31 or workspace too small";
+    case HGM_E_ROUND_LIMIT: return "round limit reached with live edges remaining";
+    case HGM_E_HIP: return "HIP runtime error";
+    default: return "unknown error code";
+    }
+}
+
+size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts) {
+    Opts o;
+    if (resolve_opts(opts, &o) != HGM_OK || !g) return 0;
+    bind_graph(&o, g);
+    if (g->n < 0 || g->m < 0 || g->kappa < 0 || g->kappa >= ((int64_t)1 << 31)) return 0;
+    return make_layout(g->n, g->m, g->kappa, o).total;
+}
+
+int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *workspace,
+              size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats) {
+    Opts o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != HGM_OK) return rc;
+    rc = check_graph(gin, o);
+    if (rc != HGM_OK) return rc;
+    bind_graph(&o, gin);
+    if (gin->m > 0 && !matched_bits) return HGM_E_ARG;
+    if (stats && stats->cap < 0) return HGM_E_ARG;
+    const Layout lay = make_layout(gin->n, gin->m, gin->kappa, o);
+    if (!workspace) return HGM_E_ARG;
+    if (ws_bytes < lay.total) return HGM_E_SIZE;
+    if (((uintptr_t)workspace & 255) != 0) return HGM_E_ARG;
+
+    Graph g;
+    memset(&g, 0, sizeof(g));
+    g.n = gin->n;
+    g.m = gin->m;
+    g.kappa = gin->kappa;
+    g.words = ((int64_t)gin->m + 31) / 32;
+    g.e_off = gin->e_off;
+    g.e_pins = gin->e_pins;
+    g.v_off = gin->v_off;
+    g.v_edges = gin->v_edges;
+    g.w = gin->w;
+    const State s = carve(workspace, lay, o);
+    Launch L;
+    L.grid = device_grid();
+    L.stream = (hipStream_t)stream;
+    if (L.grid <= 0) return HGM_E_HIP;
+    return run_rounds(g, o, lay, s, L, seed, matched_bits, stats, nullptr);
+}
+
+size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts) {
+    Opts o;
+    if (resolve_opts(opts, &o) != HGM_OK || check_batch(b, o) != HGM_OK) return 0;
+    bind_batch(&o, b);
+    return make_layout(b->n_total, b->m_total, b->kappa_total, o, true).total;
+}
+
+int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace, size_t ws_bytes,
+                    const hgm_opts *opts, void *stream, hgm_stats *stats) {
+    Opts o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != HGM_OK) return rc;
+    rc = check_batch(b, o);
+    if (rc != HGM_OK) return rc;
+    bind_batch(&o, b);
+    if (b->m_total > 0 && !matched_bits) return HGM_E_ARG;
+    if (stats && stats->cap < 0) return HGM_E_ARG;
+    const Layout lay = make_layout(b->n_total, b->m_total, b->kappa_total, o, true);
+    if (!workspace) return HGM_E_ARG;
+    if (ws_bytes < lay.total) return HGM_E_SIZE;
+    if (((uintptr_t)workspace & 255) != 0) return HGM_E_ARG;
+
+    const State s = carve(workspace, lay, o);
+    char *base = (char *)workspace;
+    BatchIn in;
+    in.count = b->count;
+    in.v_base = b->v_base;
+    in.e_base = b->e_base;
+    in.pin_base = b->pin_base;
+    in.word_base = b->word_base;
+    in.e_off = b->e_off;
+    in.v_off = o.have_vertex_side ? b->v_off : nullptr;
+    in.seeds = b->seeds;
+    in.goff = (int32_t *)(base + lay.goff);
+    in.vbase = (int32_t *)(base + lay.vbase);
+    in.bitoff = (int32_t *)(base + lay.bitoff);
+    in.gvoff = o.have_vertex_side ? (int32_t *)(base + lay.gvoff) : nullptr;
+    in.ebase = o.have_vertex_side ? (int32_t *)(base + lay.ebase) : nullptr;
+
+    Graph g;
+    memset(&g, 0, sizeof(g));
+    g.n = (int32_t)b->n_total;
+    g.m = (int32_t)b->m_total;
+    g.kappa = b->kappa_total;
+    g.words = b->words_total;
+    g.e_off = in.goff;
+    g.e_pins = b->e_pins;
+    g.v_off = in.gvoff;
+    g.v_edges = b->v_edges;
+    g.w = b->w;
+    g.vbase = in.vbase;
+    g.bitoff = in.bitoff;
+    g.ebase = in.ebase;
+    Launch L;
+    L.grid = device_grid();
+    L.stream = (hipStream_t)stream;
+    if (L.grid <= 0) return HGM_E_HIP;
+    return run_rounds(g, o, lay, s, L, 0, matched_bits, stats, &in);
 }
 
 }  // extern "C"

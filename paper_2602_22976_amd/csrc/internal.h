@@ -25,14 +25,37 @@ struct RoundStats {
     unsigned long long form;           // round 0 only: 1 edge-centric, 2 vertex-centric maximum
 };
 
+// The hypergraph as the kernels see it.  A batch of independent instances is
+// matched as their disjoint union: e_off / v_off are then global offsets built
+// by k_batch_setup, while e_pins / v_edges keep the caller's instance-local
+// ids, turned global by adding the per-edge vertex base / per-vertex edge
+// base.  For one instance the three base arrays are NULL (all zero).
 struct Graph {
     int32_t n, m;
     int64_t kappa;
+    int64_t words;           // bitmap words
     const int32_t *e_off;
     const int32_t *e_pins;
     const int32_t *v_off;
     const int32_t *v_edges;
     const uint32_t *w;
+    const int32_t *vbase;    // [m] added to the pins of edge e (batch)
+    const int32_t *bitoff;   // [m] bitmap bit of edge e is e + bitoff[e] (batch)
+    const int32_t *ebase;    // [n] added to the incident edges of vertex v (batch)
+};
+
+// Caller's batch arrays (device), for k_batch_setup.
+struct BatchIn {
+    int32_t count;
+    const int64_t *v_base, *e_base, *pin_base, *word_base;  // [count + 1]
+    const int32_t *e_off;     // [m_total + count] local offsets, instance i at e_base[i] + i
+    const int32_t *v_off;     // [n_total + count] local offsets, instance i at v_base[i] + i
+    const uint32_t *seeds;    // [count]
+    int32_t *goff;            // out [m_total + 1]
+    int32_t *vbase;           // out [m_total]
+    int32_t *bitoff;          // out [m_total]
+    int32_t *gvoff;           // out [n_total + 1] (NULL: no vertex side)
+    int32_t *ebase;           // out [n_total]
 };
 
 // Device state of one hgm_match call, carved out of the caller's workspace.
@@ -73,8 +96,10 @@ struct Launch {
 // init_flags: which optional setup k_init performs.
 constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
 constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
+constexpr int kInitKeysDone = 4; // keys were written by k_batch_setup
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
                        uint32_t *bits, int init_flags);
+hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s);
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter);

@@ -124,6 +124,7 @@ struct ChunkLds {
     int base[kBlock];         // offset of each item's list in the pin / edge array
     uint64_t key[kBlock];     // edge keys (edge chunks) or running maxima (vertex chunks)
     int flag[kBlock];         // per-item flag (failed test / retired)
+    int vb[kBlock];           // per-item id base (batch: vertex base of an edge, edge base of a vertex)
     int wave_tmp[kWaves];
     unsigned long long sum_tmp[kWaves];
 };
@@ -144,7 +145,7 @@ __device__ __forceinline__ void chunk_pins(const ChunkLds &L, const int32_t *e_p
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-        pin[u] = j[u] >= 0 ? e_pins[L.base[j[u]] + (t0 + u * kBlock - L.start[j[u]])] : 0;
+        pin[u] = j[u] >= 0 ? e_pins[L.base[j[u]] + (t0 + u * kBlock - L.start[j[u]])] + L.vb[j[u]] : 0;
 }
 
 // Raises best[pin] to the chunk items' keys over a flattened loop.  The
@@ -157,7 +158,7 @@ __device__ __forceinline__ void scatter_chunk(const ChunkLds &L, const int32_t *
                                               uint64_t *best) {
     for (int t = threadIdx.x; t < total; t += kBlock) {
         const int j = find_item(L.start, t);
-        const int pin = e_pins[L.base[j] + (t - L.start[j])];
+        const int pin = e_pins[L.base[j] + (t - L.start[j])] + L.vb[j];
         const uint64_t k = L.key[j];
         if (load_lower_bound(&best[pin]) < k) atomic_max_u64(&best[pin], k);
     }
@@ -185,14 +186,19 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
                                                  int flags) {
     __shared__ unsigned long long sum_tmp[kWaves];
     unsigned long long hot = 0;
-    const int64_t words = ((int64_t)g.m + 31) / 32;
+    const int64_t words = g.words;
     const int64_t span = g.m > g.n ? g.m : g.n;
     const int64_t top = span > words ? span : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
         if (i < g.m) {
-            uint64_t k = ((uint64_t)g.w[i] << 32) | priority_hash(seed, (uint32_t)i);
-            s.key[i] = k;
+            uint64_t k;
+            if (flags & kInitKeysDone) {
+                k = s.key[i];
+            } else {
+                k = ((uint64_t)g.w[i] << 32) | priority_hash(seed, (uint32_t)i);
+                s.key[i] = k;
+            }
             if (flags & kInitLiveKey) s.live_key[i] = k;
         }
         if (i < g.n) {
@@ -289,17 +295,20 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
         const int i = c0 + threadIdx.x;
         int len = 0, base = 0;
         uint64_t key = 0;
+        int vb = 0;
         if (i < cnt) {
             const int e = region_item(s, 0, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
             key = s.key[e];
+            if (g.vbase) vb = g.vbase[e];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
         L.start[threadIdx.x] = st;
         L.base[threadIdx.x] = base;
         L.key[threadIdx.x] = key;
+        L.vb[threadIdx.x] = vb;
         __syncthreads();
         scatter_chunk(L, g.e_pins, total, best);
         __syncthreads();
@@ -343,11 +352,13 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
+        int vb = 0;
         if (i < cnt) {
             e = region_item(s, round - 1, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
             key = s.key[e];
+            if (g.vbase) vb = g.vbase[e];
         }
         // One lane per edge, stopping at the first done pin: most retired
         // edges are found after one or two reads, survivors read all pins.
@@ -355,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         for (int k0 = 0; k0 < len && !dead; k0 += kUnroll) {
             int p[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] : -1;
+            for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] + vb : -1;
             uint8_t dv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) dv[u] = p[u] >= 0 ? s.done[p[u]] : 0;
@@ -365,6 +376,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         const int alive = (e >= 0 && len > 0 && !dead) ? 1 : 0;
         L.base[threadIdx.x] = base;
         L.key[threadIdx.x] = key;
+        L.vb[threadIdx.x] = vb;
         if (!scatter && e >= 0 && !alive) s.live_key[e] = 0;
         int n_alive;
         int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
@@ -403,7 +415,11 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // later rounds gather live_key (0 once the edge left the live set).
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
                                                uint32_t seed, int e) {
-    if (round == 0) return ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)e);
+    if (round == 0) {
+        // A batch's keys depend on each instance's seed and local ids: read them.
+        if (g.vbase) return s.key[e];
+        return ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)e);
+    }
     return s.live_key[e];
 }
 
@@ -420,9 +436,10 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         if (s.done[v]) continue;
         const int p0 = g.v_off[v] + pc.y * kHubPiece;
         const int p1 = min(g.v_off[v + 1], p0 + kHubPiece);
+        const int eb = g.ebase ? g.ebase[v] : 0;
         uint64_t mx = 0;
         for (int i = p0 + threadIdx.x; i < p1; i += kBlock) {
-            uint64_t k = vertex_key(g, s, round, seed, g.v_edges[i]);
+            uint64_t k = vertex_key(g, s, round, seed, g.v_edges[i] + eb);
             mx = k > mx ? k : mx;
         }
 #pragma unroll
@@ -435,19 +452,21 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
 
     for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < g.n; c0 += (int64_t)gridDim.x * kBlock) {
         const int v = (int)c0 + threadIdx.x;
-        int len = 0, base = 0;
+        int len = 0, base = 0, eb = 0;
         bool own = false;
         if (v < g.n && !s.done[v]) {
             base = g.v_off[v];
             len = g.v_off[v + 1] - base;
             own = len <= hub_threshold;
             if (!own) len = 0;
+            if (g.ebase) eb = g.ebase[v];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
         L.start[threadIdx.x] = st;
         L.base[threadIdx.x] = base;
         L.key[threadIdx.x] = 0;
+        L.vb[threadIdx.x] = eb;
         __syncthreads();
         for (int t0 = 0; t0 < total; t0 += kBlock) {
             const int t = t0 + threadIdx.x;
@@ -455,7 +474,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             uint64_t k = 0;
             if (t < total) {
                 j = find_item(L.start, t);
-                k = vertex_key(g, s, round, seed, g.v_edges[L.base[j] + (t - L.start[j])]);
+                k = vertex_key(g, s, round, seed, g.v_edges[L.base[j] + (t - L.start[j])] + L.vb[j]);
             }
             // segmented inclusive max-scan over the wave, segments = equal j
 #pragma unroll
@@ -551,22 +570,24 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
+        int vb = 0;
         if (i < cnt) {
             e = region_item(s, round, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
             key = s.key[e];
+            if (g.vbase) vb = g.vbase[e];
         }
         int matched;
         if (!clear_pins) {
             // One lane per edge, stopping at the first pin where the edge is
             // not the maximum: almost every edge fails at its first pin.
             // The first pin alone, then the rest kUnroll at a time.
-            bool ok = e >= 0 && (len == 0 || best[g.e_pins[base]] == key);
+            bool ok = e >= 0 && (len == 0 || best[g.e_pins[base] + vb] == key);
             for (int k0 = 1; k0 < len && ok; k0 += kUnroll) {
                 int p[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] : -1;
+                for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] + vb : -1;
                 uint64_t bv[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) bv[u] = p[u] >= 0 ? best[p[u]] : key;
@@ -583,6 +604,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             L.base[threadIdx.x] = base;
             L.key[threadIdx.x] = key;
             L.flag[threadIdx.x] = 0;
+            L.vb[threadIdx.x] = vb;
             __syncthreads();
             for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
                 int j[kUnroll], pin[kUnroll];
@@ -602,11 +624,12 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             __syncthreads();
         }
         if (matched) {
-            atomicOr(&bits[e >> 5], 1u << (e & 31));
+            const int bit = g.bitoff ? e + g.bitoff[e] : e;
+            atomicOr(&bits[bit >> 5], 1u << (bit & 31));
             nm += 1;
             wm += key >> 32;
             pm += (unsigned long long)len;
-            for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k]] = 1;
+            for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k] + vb] = 1;
         }
     }
     nm = block_sum_u64(nm, L.sum_tmp);
@@ -616,6 +639,39 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
         atomicAdd(&st_cur->matched[b % kSub], nm);
         atomicAdd(&st_cur->weight[b % kSub], wm);
         atomicAdd(&st_cur->mpins[b % kSub], pm);
+    }
+}
+
+// Batch setup (one workgroup per instance): global pin and incidence
+// offsets, per-edge vertex base and bitmap offset, per-vertex edge base, and
+// keys w << 32 | H(seed_i, local id) with each instance's own seed.  Each
+// instance's bitmap starts at bit 32 * word_base[i].
+__global__ void __launch_bounds__(kBlock) k_batch_setup(Graph g, BatchIn b, State s) {
+    for (int i = blockIdx.x; i < b.count; i += gridDim.x) {
+        const int64_t eb = b.e_base[i], ne = b.e_base[i + 1] - eb;
+        const int64_t vb = b.v_base[i], nv = b.v_base[i + 1] - vb;
+        const int64_t pb = b.pin_base[i];
+        const int64_t wb = b.word_base[i];
+        const uint32_t seed = b.seeds[i];
+        const int32_t *eo = b.e_off + eb + i;
+        for (int64_t el = threadIdx.x; el < ne; el += kBlock) {
+            const int64_t e = eb + el;
+            b.goff[e] = (int32_t)(pb + eo[el]);
+            b.vbase[e] = (int32_t)vb;
+            b.bitoff[e] = (int32_t)(32 * wb - eb);
+            s.key[e] = ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)el);
+        }
+        if (b.gvoff) {
+            const int32_t *vo = b.v_off + vb + i;
+            for (int64_t vl = threadIdx.x; vl < nv; vl += kBlock) {
+                b.gvoff[vb + vl] = (int32_t)(pb + vo[vl]);
+                b.ebase[vb + vl] = (int32_t)eb;
+            }
+        }
+        if (i == b.count - 1 && threadIdx.x == 0) {
+            b.goff[g.m] = (int32_t)b.pin_base[b.count];
+            if (b.gvoff) b.gvoff[g.n] = (int32_t)b.pin_base[b.count];
+        }
     }
 }
 
@@ -631,6 +687,13 @@ hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const Sta
     hipLaunchKernelGGL(k_prologue, dim3(1), dim3(kBlock), 0, L.stream, g, s);
     hipLaunchKernelGGL(k_init, dim3(L.grid), dim3(kBlock), 0, L.stream, g, seed, s, bits,
                        init_flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s) {
+    const int grid = b.count < L.grid ? b.count : L.grid;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_setup, dim3(grid), dim3(kBlock), 0, L.stream, g, b, s);
     return hipGetLastError();
 }
 

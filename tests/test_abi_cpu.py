@@ -101,3 +101,33 @@ def test_product_package_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "oracle_" not in text, fn
+
+
+def _batch(count, n, m, kappa, words):
+    b = hgm.HgmBatch()
+    b.count, b.n_total, b.m_total, b.kappa_total, b.words_total = count, n, m, kappa, words
+    fake = 0x1000
+    b.v_base = b.e_base = b.pin_base = b.word_base = fake
+    b.e_off = b.e_pins = b.v_off = b.v_edges = b.w = b.seeds = fake
+    return b
+
+
+def test_batch_arguments_without_gpu(lib):
+    ok = _batch(4, 100, 200, 800, 8)
+    size = hgm.hgm_batch_workspace_size(ok)
+    assert size > hgm.hgm_workspace_size(_csr(100, 200, 800))   # plus global offsets
+    assert hgm.hgm_batch_workspace_size(_batch(-1, 1, 1, 1, 1)) == 0
+    assert hgm.hgm_batch_workspace_size(_batch(1, 1, 1, 2 ** 31, 1)) == 0
+    assert hgm.hgm_batch_workspace_size(_batch(1, 1, 1, 1, 2 ** 27)) == 0
+    ws, bits = 0x100000, 0x2000
+    assert hgm.hgm_match_batch(_batch(-1, 1, 1, 1, 1), bits, ws, 1 << 30) == hgm.HGM_E_ARG
+    assert hgm.hgm_match_batch(_batch(1, 1, 1, 2 ** 31, 1), bits, ws, 1 << 30) == hgm.HGM_E_SIZE
+    assert hgm.hgm_match_batch(ok, bits, ws, 64) == hgm.HGM_E_SIZE
+    assert hgm.hgm_match_batch(ok, 0, ws, 1 << 30) == hgm.HGM_E_ARG
+    assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(validate=True)) == hgm.HGM_E_ARG
+    b = _batch(4, 100, 200, 800, 8)
+    b.seeds = None
+    assert hgm.hgm_match_batch(b, bits, ws, 1 << 30) == hgm.HGM_E_ARG
+    b = _batch(0, 0, 5, 5, 1)   # edges but no instance
+    assert hgm.hgm_match_batch(b, bits, ws, 1 << 30) == hgm.HGM_E_ARG
+    assert lib.hgm_match_batch(None, None, None, 0, None, None, None) == hgm.HGM_E_ARG

@@ -1,0 +1,121 @@
+"""GPU parity of hgm_match_batch: every instance's bitmap segment equals the
+oracle's greedy matching for that instance and seed, and equals hgm_match on
+the instance alone; the aggregate per-round counts equal the sum of the
+instances' oracle round counts."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = ["auto", "crcw", "crew"]
+
+
+@pytest.fixture(scope="module")
+def hgm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_22976_amd as lib
+    lib.load()
+    return lib
+
+
+def _segments(b, bits):
+    out = []
+    for i in range(b.count):
+        w0, w1 = int(b.word_base[i]), int(b.word_base[i + 1])
+        out.append(bits[w0:w1])
+    return out
+
+
+def _oracle_batch(b):
+    per, rounds = [], []
+    for i in range(b.count):
+        g = b.instance(i)
+        seed = int(b.seeds[i])
+        bits, cnt, wt = oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, seed)
+        _, st = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed)
+        per.append((bits, cnt, wt))
+        rounds.append(st)
+    return per, rounds
+
+
+def _agg(rounds, key):
+    R = max([st["rounds"] for st in rounds] + [0])
+    tot = np.zeros(R, dtype=np.int64)
+    for st in rounds:
+        a = st[key]
+        tot[:a.size] += a
+    return tot
+
+
+def _check_batch(hgm, b, variant, per=None, rounds=None):
+    import torch
+    if per is None:
+        per, rounds = _oracle_batch(b)
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    bits, st = hgm.match_batch(db, hgm.make_opts(variant))
+    torch.cuda.synchronize()
+    got = bits.cpu().numpy().view(np.uint32)
+    segs = _segments(b, got)
+    for i, (exp, _, _) in enumerate(per):
+        assert np.array_equal(segs[i], exp), f"instance {i} differs ({variant})"
+    assert st["matched"] == sum(p[1] for p in per)
+    assert st["weight"] == sum(p[2] for p in per)
+    assert st["rounds"] == max([r["rounds"] for r in rounds] + [0])
+    assert np.array_equal(st["live_edges"], _agg(rounds, "live_edges"))
+    assert np.array_equal(st["live_pins"], _agg(rounds, "live_pins"))
+    assert np.array_equal(st["matched_per_round"], _agg(rounds, "matched_per_round"))
+    return got
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_small_batch(hgm, variant):
+    b = synth.config_batched(seed=77, count=96, n_lo=20, n_hi=3000)
+    print(f"batch count={b.count} m_total={int(b.e_base[-1])} variant={variant}", flush=True)
+    _check_batch(hgm, b, variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_degenerate_batches(hgm, variant):
+    rng = np.random.default_rng(3)
+    gs = [synth.from_edge_lists(0, [], []),                          # empty instance
+          synth.random_instance(5, 40, 70, 2, 4, 1, 9),
+          synth.from_edge_lists(3, [[], [0, 1], []], [4, 5, 6]),     # empty edges
+          synth.from_edge_lists(5, [], []),                          # vertices, no edges
+          synth.random_instance(6, 7, 33, 1, 3, 0, 2, empty_frac=0.2),
+          synth.from_edge_lists(1, [[0]], [3])]
+    seeds = rng.integers(0, 2 ** 32, size=len(gs)).astype(np.uint32)
+    b = synth.batch_from_instances(gs, seeds)
+    print(f"degenerate batch variant={variant}", flush=True)
+    _check_batch(hgm, b, variant)
+    one = synth.batch_from_instances([gs[1]], seeds[:1])
+    _check_batch(hgm, one, variant)
+
+
+def test_batch_equals_single_calls(hgm):
+    import torch
+    b = synth.config_batched(seed=5, count=40, n_lo=100, n_hi=5000)
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    bits, _ = hgm.match_batch(db, hgm.make_opts("auto"))
+    segs = _segments(b, bits.cpu().numpy().view(np.uint32))
+    for i in range(b.count):
+        g = b.instance(i)
+        dg = hgm.DeviceHypergraph.from_host(g, "cuda:0")
+        one, _ = hgm.match(dg, int(b.seeds[i]), hgm.make_opts("auto"))
+        torch.cuda.synchronize()
+        assert np.array_equal(one.cpu().numpy().view(np.uint32), segs[i]), i
+
+
+def test_batch_workload_sample(hgm):
+    """512 instances with the batched workload's distribution (n log-uniform
+    in [100, 50,000], m = 2n, |e| ~ U{2..12}, seeds = instance index)."""
+    b = synth.config_batched(seed=1004, count=512)
+    print(f"batched workload sample: m_total={int(b.e_base[-1])} "
+          f"kappa_total={int(b.pin_base[-1])}", flush=True)
+    per, rounds = _oracle_batch(b)
+    for variant in ("auto", "crcw"):
+        _check_batch(hgm, b, variant, per, rounds)
