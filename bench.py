@@ -125,6 +125,62 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
 
 
+def batched_leg(count, steps):
+    """Batched vs plain hypergraphs/s on `count` instances of the batched
+    workload (n log-uniform in [100, 50,000], m = 2n, |e| ~ U{2..12},
+    w ~ U{1..1000}, seed of instance i = i).  Batched: one hgm_match_batch
+    call for all instances.  Plain: one hgm_match call per instance on the
+    same device-resident arrays (each instance's slice is a standalone CSR),
+    with one reused workspace."""
+    import numpy as np
+    import torch
+    import paper_2602_22976_amd as hgm
+    import synth
+    t0 = time.perf_counter()
+    b = synth.config_batched(seed=1004, count=count)
+    gen_s = time.perf_counter() - t0
+    dev = "cuda:0"
+    db = hgm.DeviceBatch.from_host(b, dev)
+    opts = hgm.make_opts("auto")
+    ws = hgm.alloc_batch_workspace(db, opts)
+    bits = torch.empty(max(db.words_total, 1), dtype=torch.int32, device=dev)
+    hgm.match_batch(db, opts, workspace=ws, bits=bits, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = hgm.match_batch(db, opts, workspace=ws, bits=bits, want_stats=True)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    batch_bits = bits.clone()
+
+    views = []
+    wmax = 0
+    for i in range(b.count):
+        n, m = int(b.n[i]), int(b.m[i])
+        eb, vb, pb = int(b.e_base[i]), int(b.v_base[i]), int(b.pin_base[i])
+        kap = int(b.pin_base[i + 1]) - pb
+        dg = hgm.DeviceHypergraph(n, m, db.e_off[eb + i: eb + i + m + 1], db.e_pins[pb: pb + kap],
+                                  db.v_off[vb + i: vb + i + n + 1], db.v_edges[pb: pb + kap],
+                                  db.w[eb: eb + m])
+        wb0, wb1 = int(b.word_base[i]), int(b.word_base[i + 1])
+        views.append((dg, int(b.seeds[i]), bits[wb0:wb1] if wb1 > wb0 else bits[:1]))
+        wmax = max(wmax, hgm.hgm_workspace_size(dg.csr(), opts))
+    pws = torch.empty(wmax, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for dg, seed, bv in views:
+        hgm.match(dg, seed, opts, workspace=pws, bits=bv, want_stats=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = bool(torch.equal(bits, batch_bits))
+    return {"instances": count, "m_total": int(b.e_base[-1]), "kappa_total": int(b.pin_base[-1]),
+            "generated_s": round(gen_s, 1), "rounds": st["rounds"],
+            "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3,
+            "hypergraphs_per_s_batched": count / t_batch,
+            "hypergraphs_per_s_plain": count / t_plain,
+            "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same}
+
+
 def cpu_baseline(g, seed, budget_s):
     import numpy as np
     import oracle
@@ -157,6 +213,8 @@ def main():
     ap.add_argument("--rounds-per-sync", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=float, default=10.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--batch-count", type=int, default=4096,
+                    help="instances in the batched-vs-plain leg (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
     args = ap.parse_args()
@@ -266,8 +324,11 @@ def main():
         "per_round": {"live_edges": [int(x) for x in st["live_edges"]],
                       "live_pins": [int(x) for x in st["live_pins"]],
                       "round_ms": [round(float(x), 4) for x in sti["round_ms"]]},
+        "batched": None,
         "cpu_baseline": None,
     }
+    if args.batch_count > 0:
+        result["batched"] = batched_leg(args.batch_count, max(1, min(args.steps, 5)))
     if args.cpu_baseline > 0:
         result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
     print(json.dumps(result), flush=True)

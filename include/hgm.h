@@ -186,6 +186,67 @@ size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts);
 int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace, size_t ws_bytes,
                     const hgm_opts *opts, void *stream, hgm_stats *stats);
 
+/* ---------------------------------------------------------------------------
+ * Request server: continuous batching of matching requests on one GPU.
+ *
+ * The caller gives the server a device arena (its HBM budget).  Requests
+ * (host arrays) are queued by hgm_server_submit.  Worker threads, each with
+ * its own HIP stream, take turns forming a wave from every queued request
+ * that fits the arena's free memory (arrival order, at most max_batch),
+ * upload it into one arena block, match it with hgm_match_batch and copy each
+ * request's bitmap back; requests arriving meanwhile go into the next wave,
+ * which another worker runs concurrently.  A wave's memory returns to the
+ * arena when it completes, admitting waiting requests.  A request's bitmap is
+ * exactly hgm_match's for that instance and seed, whatever it ran with.  A
+ * request larger than the whole arena completes with status HGM_E_SIZE. */
+typedef struct hgm_request {
+    int64_t id;              /* caller's tag, echoed in the result */
+    int32_t n, m;
+    int64_t kappa;
+    const int32_t *e_off;    /* HOST arrays in the hgm_csr layout (vertex side */
+    const int32_t *e_pins;   /* required); they must stay valid until the */
+    const int32_t *v_off;    /* request's result has been polled.  Pinned */
+    const int32_t *v_edges;  /* host memory makes the uploads asynchronous. */
+    const uint32_t *w;
+    uint32_t seed;
+    uint32_t *bits_out;      /* HOST, ceil(m/32) words, written before the result is posted */
+} hgm_request;
+
+typedef struct hgm_result {
+    int64_t id;
+    int32_t status;          /* HGM_OK or an HGM_E_* code */
+    int32_t wave_size;       /* requests matched together with this one */
+    double t_submit;         /* steady-clock seconds: submitted, admitted into a */
+    double t_admit;          /* wave (memory reserved), bitmap copied back */
+    double t_done;
+} hgm_result;
+
+typedef struct hgm_server_opts {
+    int32_t workers;         /* concurrent waves (threads and streams); 0 = 2 */
+    int32_t max_batch;       /* requests per wave at most; 0 = 1024 */
+    hgm_opts match;          /* options of every wave's matching (validate unsupported) */
+} hgm_server_opts;
+
+typedef struct hgm_server_state {
+    int64_t queued, submitted, completed;
+    uint64_t arena_bytes, arena_used, arena_peak;  /* peak never exceeds arena_bytes */
+} hgm_server_state;
+
+typedef struct hgm_server hgm_server;
+
+/* arena: device memory, 256-byte aligned, owned by the caller and unused by
+ * it until hgm_server_destroy returns.  The current device is the server's. */
+int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *opts,
+                      hgm_server **out);
+/* Queues a request (non-blocking, thread-safe). */
+int hgm_server_submit(hgm_server *server, const hgm_request *req);
+/* Moves up to `cap` finished results to `out`, waiting up to timeout_s
+ * seconds for the first; returns how many were written (or an HGM_E_* code). */
+int hgm_server_poll(hgm_server *server, hgm_result *out, int cap, double timeout_s);
+int hgm_server_info(hgm_server *server, hgm_server_state *state);
+/* Finishes every queued request, stops the workers and frees the server. */
+int hgm_server_destroy(hgm_server *server);
+
 /* Short English description of an HGM_* code (static storage). */
 const char *hgm_strerror(int code);
 

@@ -26,7 +26,8 @@ HGM_VARIANT_CREW = 2
 VARIANTS = {"auto": HGM_VARIANT_AUTO, "crcw": HGM_VARIANT_CRCW, "crew": HGM_VARIANT_CREW}
 
 EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_batch_workspace_size", "hgm_match_batch",
-            "hgm_strerror", "hgm_version"]
+            "hgm_server_create", "hgm_server_submit", "hgm_server_poll", "hgm_server_info",
+            "hgm_server_destroy", "hgm_strerror", "hgm_version"]
 
 
 class HgmCsr(ctypes.Structure):
@@ -50,6 +51,29 @@ class HgmBatch(ctypes.Structure):
                 ("e_off", ctypes.c_void_p), ("e_pins", ctypes.c_void_p),
                 ("v_off", ctypes.c_void_p), ("v_edges", ctypes.c_void_p),
                 ("w", ctypes.c_void_p), ("seeds", ctypes.c_void_p)]
+
+
+class HgmRequest(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("kappa", ctypes.c_int64), ("e_off", ctypes.c_void_p), ("e_pins", ctypes.c_void_p),
+                ("v_off", ctypes.c_void_p), ("v_edges", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("seed", ctypes.c_uint32), ("bits_out", ctypes.c_void_p)]
+
+
+class HgmResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("wave_size", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class HgmServerOpts(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("match", HgmOpts)]
+
+
+class HgmServerState(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("submitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("arena_bytes", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
 
 
 HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE = range(5)
@@ -96,6 +120,17 @@ def load():
     lib.hgm_match_batch.restype = ctypes.c_int
     lib.hgm_match_batch.argtypes = [ctypes.POINTER(HgmBatch), P, P, ctypes.c_size_t,
                                     ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
+    lib.hgm_server_create.restype = ctypes.c_int
+    lib.hgm_server_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(HgmServerOpts),
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.hgm_server_submit.restype = ctypes.c_int
+    lib.hgm_server_submit.argtypes = [P, ctypes.POINTER(HgmRequest)]
+    lib.hgm_server_poll.restype = ctypes.c_int
+    lib.hgm_server_poll.argtypes = [P, ctypes.POINTER(HgmResult), ctypes.c_int, ctypes.c_double]
+    lib.hgm_server_info.restype = ctypes.c_int
+    lib.hgm_server_info.argtypes = [P, ctypes.POINTER(HgmServerState)]
+    lib.hgm_server_destroy.restype = ctypes.c_int
+    lib.hgm_server_destroy.argtypes = [P]
     lib.hgm_strerror.restype = ctypes.c_char_p
     lib.hgm_strerror.argtypes = [ctypes.c_int]
     lib.hgm_version.restype = ctypes.c_int
@@ -323,3 +358,85 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
     if rc != HGM_OK:
         raise HgmError(rc, "hgm_match")
     return bits[:words], (_stats_dict(st, arrays, rms, timing) if st is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# Request server (hgm_server_*): marshalling and bookkeeping of host buffers.
+
+class Server:
+    """Continuous-batching request server over a torch-allocated device arena.
+
+    submit() takes a host hypergraph (numpy arrays, pinned or not), keeps its
+    arrays alive until the result is polled, and returns the request id;
+    poll() returns finished results as dicts with the output bitmap."""
+
+    def __init__(self, arena_bytes, workers=2, max_batch=0, opts: HgmOpts | None = None,
+                 device="cuda:0"):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        so = HgmServerOpts()
+        so.workers, so.max_batch = workers, max_batch
+        if opts is not None:
+            so.match = opts
+        h = ctypes.c_void_p()
+        rc = load().hgm_server_create(self.arena.data_ptr(), self.arena.numel(),
+                                      ctypes.byref(so), ctypes.byref(h))
+        if rc != HGM_OK:
+            raise HgmError(rc, "hgm_server_create")
+        self.h = h
+        self.live = {}
+        self.next_id = 0
+
+    def submit(self, g, seed, req_id=None):
+        import numpy as np
+        rid = self.next_id if req_id is None else int(req_id)
+        self.next_id = max(self.next_id, rid) + 1
+        arrs = [np.ascontiguousarray(g.e_off, dtype=np.int32),
+                np.ascontiguousarray(g.e_pins, dtype=np.int32),
+                np.ascontiguousarray(g.v_off, dtype=np.int32),
+                np.ascontiguousarray(g.v_edges, dtype=np.int32),
+                np.ascontiguousarray(g.w, dtype=np.uint32)]
+        out = np.zeros(max((g.m + 31) // 32, 1), dtype=np.uint32)
+        q = HgmRequest()
+        q.id, q.n, q.m, q.kappa = rid, g.n, g.m, int(arrs[1].size)
+        q.e_off, q.e_pins, q.v_off, q.v_edges, q.w = [a.ctypes.data_as(ctypes.c_void_p)
+                                                      for a in arrs]
+        q.seed = seed & 0xFFFFFFFF
+        q.bits_out = out.ctypes.data_as(ctypes.c_void_p)
+        self.live[rid] = (arrs, out, g.m)
+        rc = load().hgm_server_submit(self.h, ctypes.byref(q))
+        if rc != HGM_OK:
+            del self.live[rid]
+            raise HgmError(rc, "hgm_server_submit")
+        return rid
+
+    def poll(self, cap=256, timeout_s=0.0):
+        buf = (HgmResult * cap)()
+        k = load().hgm_server_poll(self.h, buf, cap, float(timeout_s))
+        if k < 0:
+            raise HgmError(k, "hgm_server_poll")
+        res = []
+        for r in buf[:k]:
+            arrs, out, m = self.live.pop(r.id)
+            res.append({"id": r.id, "status": r.status, "wave_size": r.wave_size,
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done,
+                        "bits": out[:(m + 31) // 32]})
+        return res
+
+    def info(self):
+        st = HgmServerState()
+        rc = load().hgm_server_info(self.h, ctypes.byref(st))
+        if rc != HGM_OK:
+            raise HgmError(rc, "hgm_server_info")
+        return {f: getattr(st, f) for f, _ in HgmServerState._fields_}
+
+    def close(self):
+        if self.h:
+            load().hgm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

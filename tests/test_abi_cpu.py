@@ -131,3 +131,20 @@ def test_batch_arguments_without_gpu(lib):
     b = _batch(0, 0, 5, 5, 1)   # edges but no instance
     assert hgm.hgm_match_batch(b, bits, ws, 1 << 30) == hgm.HGM_E_ARG
     assert lib.hgm_match_batch(None, None, None, 0, None, None, None) == hgm.HGM_E_ARG
+
+
+def test_server_arguments_without_gpu(lib):
+    h = ctypes.c_void_p()
+    so = hgm.HgmServerOpts()
+    assert lib.hgm_server_create(None, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    assert lib.hgm_server_create(0x1000, 0, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    assert lib.hgm_server_create(0x1008, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    so.workers = -1
+    assert lib.hgm_server_create(0x1000, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    so.workers = 0
+    so.match.validate = 1
+    assert lib.hgm_server_create(0x1000, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    assert lib.hgm_server_submit(None, None) == hgm.HGM_E_ARG
+    assert lib.hgm_server_poll(None, None, 0, 0.0) == hgm.HGM_E_ARG
+    assert lib.hgm_server_info(None, None) == hgm.HGM_E_ARG
+    assert lib.hgm_server_destroy(None) == hgm.HGM_E_ARG

@@ -1,0 +1,116 @@
+"""The request server: every request's bitmap is the same in the mix as
+alone (and equals the oracle), admission never exceeds the HBM budget,
+requests beyond the budget wait, requests that arrive while others run are
+admitted and their waves overlap on the device."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hgm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_22976_amd as lib
+    lib.load()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def pool():
+    """Mixed sizes: kappa log-uniform in [1e3, 3e5], |e| ~ U{2..32}."""
+    return synth.config_served_pool(seed=55, count=48, k_lo=1e3, k_hi=3e5)
+
+
+def _drain(srv, n, timeout=120.0):
+    got = []
+    t0 = time.time()
+    while len(got) < n:
+        got += srv.poll(cap=64, timeout_s=0.5)
+        assert time.time() - t0 < timeout, f"only {len(got)} of {n} results"
+    return got
+
+
+def _expected(pool):
+    return [oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, 1000 + i)[0]
+            for i, g in enumerate(pool)]
+
+
+def test_mix_equals_alone_and_oracle(hgm, pool):
+    import torch
+    exp = _expected(pool)
+    srv = hgm.Server(1 << 30, workers=2)
+    try:
+        # a first burst, then late arrivals while the first waves are running
+        for i in range(24):
+            srv.submit(pool[i], 1000 + i, req_id=i)
+        time.sleep(0.002)
+        for i in range(24, len(pool)):
+            srv.submit(pool[i], 1000 + i, req_id=i)
+            time.sleep(0.0005)
+        res = _drain(srv, len(pool))
+        info = srv.info()
+    finally:
+        srv.close()
+    assert info["arena_peak"] <= info["arena_bytes"]
+    for r in res:
+        assert r["status"] == 0
+        assert np.array_equal(r["bits"], exp[r["id"]]), f"request {r['id']} differs in the mix"
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+    # alone: each request through hgm_match on its own
+    for i in (0, 7, 30, len(pool) - 1):
+        dg = hgm.DeviceHypergraph.from_host(pool[i], "cuda:0")
+        bits, _ = hgm.match(dg, 1000 + i, hgm.make_opts("auto"))
+        torch.cuda.synchronize()
+        assert np.array_equal(bits.cpu().numpy().view(np.uint32), exp[i])
+    # several waves, and at least two of them overlapped in time
+    waves = {}
+    for r in res:
+        waves.setdefault((r["t_admit"], r["t_done"]), []).append(r["id"])
+    spans = sorted(waves)
+    assert len(spans) >= 2
+    overlap = any(b[0] < a[1] for a, b in zip(spans, spans[1:]))
+    assert overlap, "no two waves were on the device at the same time"
+
+
+def test_tiny_budget_queues_and_never_overcommits(hgm, pool):
+    exp = _expected(pool)
+    big = max(range(len(pool)), key=lambda i: pool[i].kappa)
+    # room for about one large request at a time
+    budget = 64 * pool[big].kappa + (8 << 20)
+    srv = hgm.Server(budget, workers=3)
+    try:
+        for i, g in enumerate(pool):
+            srv.submit(g, 1000 + i, req_id=i)
+        res = _drain(srv, len(pool))
+        info = srv.info()
+    finally:
+        srv.close()
+    assert info["arena_peak"] <= budget
+    assert all(r["status"] == 0 for r in res)
+    for r in res:
+        assert np.array_equal(r["bits"], exp[r["id"]])
+    assert max(r["wave_size"] for r in res) < len(pool)   # the budget split the work
+
+
+def test_request_larger_than_budget_fails_cleanly(hgm, pool):
+    big = max(pool, key=lambda g: g.kappa)
+    small = min(pool, key=lambda g: g.kappa)
+    srv = hgm.Server(1 << 20, workers=1)   # 1 MiB
+    try:
+        srv.submit(big, 1, req_id=0)
+        srv.submit(small, 2, req_id=1)
+        res = {r["id"]: r for r in _drain(srv, 2)}
+    finally:
+        srv.close()
+    assert res[0]["status"] == hgm.HGM_E_SIZE
+    assert res[1]["status"] == 0
+    exp = oracle.greedy(small.n, small.m, small.e_off, small.e_pins, small.w, 2)[0]
+    assert np.array_equal(res[1]["bits"], exp)
