@@ -181,6 +181,78 @@ def batched_leg(count, steps):
             "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same}
 
 
+def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2):
+    """Open-loop Poisson arrivals at `rate` req/s for `duration` s into the
+    request server.  Requests are drawn (seeded) from a pool of pre-generated
+    hypergraphs in pinned host memory (kappa log-uniform in [1e3, 1e7],
+    |e| ~ U{2..32}, m = round(kappa/17), n = max(32, round(m/2)),
+    w ~ U{1..1e6}); request i uses priority seed i.  Latency = completion
+    minus scheduled arrival (monotonic clock), over requests arriving after
+    the first `warmup_frac` of the run."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2602_22976_amd as hgm
+    import synth
+    t0 = time.perf_counter()
+    pool = synth.config_served_pool(seed=1005, count=pool_count)
+    pinned = []
+    for g in pool:   # copy every array into pinned host memory (asynchronous uploads)
+        arrs = {}
+        for name in ("e_off", "e_pins", "v_off", "v_edges"):
+            t = torch.empty(getattr(g, name).size, dtype=torch.int32, pin_memory=True)
+            t.numpy()[:] = getattr(g, name)
+            arrs[name] = t
+        t = torch.empty(g.m, dtype=torch.int32, pin_memory=True)
+        t.numpy()[:] = g.w.view(np.int32)
+        arrs["w"] = t
+        pinned.append((g, arrs))
+    views = [synth.Hypergraph(g.n, g.m, a["e_off"].numpy(), a["e_pins"].numpy(),
+                              a["v_off"].numpy(), a["v_edges"].numpy(),
+                              a["w"].numpy().view(np.uint32)) for g, a in pinned]
+    gen_s = time.perf_counter() - t0
+    arrivals = synth.gen.poisson_arrivals(2005, rate, duration)
+    pick = np.random.Generator(np.random.PCG64(3005)).integers(0, len(views), size=arrivals.size)
+    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"))
+    sched = {}
+    done = []
+    start = time.monotonic() + 0.05
+
+    def feed():
+        for i, (ta, k) in enumerate(zip(arrivals, pick)):
+            target = start + ta
+            while True:
+                dt = target - time.monotonic()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.0005))
+            sched[i] = target
+            srv.submit(views[k], i, req_id=i)
+
+    th = threading.Thread(target=feed)
+    th.start()
+    while len(done) < arrivals.size:
+        done += srv.poll(cap=1024, timeout_s=0.2)
+        if not th.is_alive() and len(done) < arrivals.size and time.monotonic() > start + duration + 120:
+            break
+    th.join()
+    info = srv.info()
+    srv.close()
+    end = max(r["t_done"] for r in done)
+    ok = [r for r in done if r["status"] == 0]
+    lat = np.array([r["t_done"] - sched[r["id"]] for r in ok if arrivals[r["id"]] >= warmup_frac * duration])
+    kap = sum(views[pick[r["id"]]].kappa for r in ok)
+    return {"rate": rate, "duration_s": duration, "requests": int(arrivals.size),
+            "completed": len(ok), "failed": len(done) - len(ok), "pool": pool_count,
+            "pool_generated_s": round(gen_s, 1), "workers": workers, "budget_gb": budget_gb,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_ms": float(lat.mean() * 1e3),
+            "hypergraphs_per_s": len(ok) / (end - start),
+            "incidences_per_s": kap / (end - start),
+            "mean_wave": float(np.mean([r["wave_size"] for r in ok])),
+            "arena_peak_gb": info["arena_peak"] / (1 << 30)}
+
+
 def cpu_baseline(g, seed, budget_s):
     import numpy as np
     import oracle
@@ -215,6 +287,12 @@ def main():
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="instances in the batched-vs-plain leg (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of the served leg (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
     args = ap.parse_args()
@@ -325,10 +403,14 @@ def main():
                       "live_pins": [int(x) for x in st["live_pins"]],
                       "round_ms": [round(float(x), 4) for x in sti["round_ms"]]},
         "batched": None,
+        "served": None,
         "cpu_baseline": None,
     }
     if args.batch_count > 0:
         result["batched"] = batched_leg(args.batch_count, max(1, min(args.steps, 5)))
+    if args.serve_seconds > 0:
+        result["served"] = served_leg(args.serve_rate, args.serve_seconds, args.serve_pool,
+                                      args.serve_budget_gb, args.serve_workers)
     if args.cpu_baseline > 0:
         result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
     print(json.dumps(result), flush=True)
