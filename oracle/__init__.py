@@ -63,12 +63,16 @@ def _load():
     lib.oracle_priorities.argtypes = [ctypes.c_uint32, ctypes.c_int32, P]
     lib.oracle_greedy.restype = ctypes.c_int
     lib.oracle_greedy.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, ctypes.c_uint32, P, P, P]
+    lib.oracle_round_priority.restype = ctypes.c_uint32
+    lib.oracle_round_priority.argtypes = [ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32]
     lib.oracle_priority_collisions.restype = ctypes.c_int64
     lib.oracle_priority_collisions.argtypes = [ctypes.c_uint32]
     lib.oracle_local_max.restype = ctypes.c_int
     lib.oracle_local_max.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P, P, P,
                                      ctypes.c_uint32, ctypes.c_int32, P, P, P, P, P,
                                      ctypes.c_int32]
+    lib.oracle_local_max_reseed.restype = ctypes.c_int
+    lib.oracle_local_max_reseed.argtypes = lib.oracle_local_max.argtypes
     _lib = lib
     return lib
 
@@ -92,6 +96,11 @@ def priorities(seed: int, m: int) -> np.ndarray:
     if m > 0:
         _load().oracle_priorities(seed & 0xFFFFFFFF, m, _ptr(out))
     return out
+
+
+def round_priority(seed: int, rnd: int, e: int) -> int:
+    """H(H(seed, round), e): the reseeded order's priority."""
+    return int(_load().oracle_round_priority(seed & 0xFFFFFFFF, rnd, e))
 
 
 def priority_collisions(seed: int) -> int:
@@ -133,8 +142,12 @@ def greedy(n, m, e_off, e_pins, w, seed):
     return bits[:n_words(m)], int(cnt.value), int(wt.value)
 
 
-def local_max(n, m, e_off, e_pins, v_off, v_edges, w, seed, max_rounds=0, cap=None):
-    """Round-based local max.  Returns (bits, stats dict)."""
+def local_max(n, m, e_off, e_pins, v_off, v_edges, w, seed, max_rounds=0, cap=None,
+              reseed=False):
+    """Round-based local max.  Returns (bits, stats dict).
+
+    reseed=True draws fresh tie-breaking priorities every round:
+    round r ranks by (w, H(H(seed, r), e), e)."""
     e_off, e_pins, v_off, v_edges = _i32(e_off), _i32(e_pins), _i32(v_off), _i32(v_edges)
     w = np.ascontiguousarray(w, dtype=np.uint32)
     if cap is None:
@@ -144,7 +157,8 @@ def local_max(n, m, e_off, e_pins, v_off, v_edges, w, seed, max_rounds=0, cap=No
     lp = np.zeros(max(cap, 1), dtype=np.int64)
     mr = np.zeros(max(cap, 1), dtype=np.int64)
     rounds = ctypes.c_int32(0)
-    rc = _load().oracle_local_max(n, m, _ptr(e_off), _ptr(e_pins), _ptr(v_off), _ptr(v_edges),
+    fn = _load().oracle_local_max_reseed if reseed else _load().oracle_local_max
+    rc = fn(n, m, _ptr(e_off), _ptr(e_pins), _ptr(v_off), _ptr(v_edges),
                                   _ptr(w), seed & 0xFFFFFFFF, max_rounds, _ptr(bits),
                                   ctypes.byref(rounds), _ptr(le), _ptr(lp), _ptr(mr), cap)
     if rc == ORACLE_E_ROUNDS:

@@ -27,6 +27,8 @@
  *    its single-core baseline (Introduction; Experiments on Hypergraphs): sort
  *    all edges by the order above, best first, and take an edge when none of
  *    its pins is taken yet.
+ *  - oracle_local_max_reseed: the same rounds with fresh tie-breaking
+ *    priorities every round (see local_max_impl).
  *  - oracle_local_max: the round-based local-max algorithm (Sequential
  *    Algorithm; Algorithm 2, CREW form) with the fixed order.  Each round every
  *    active vertex records its best active incident edge T[v]; an active edge e
@@ -166,14 +168,22 @@ int oracle_greedy(int32_t n, int32_t m, const int32_t *e_off, const int32_t *e_p
 }
 
 /* ---------------------------------------------------------------------- */
+/* Seed of round r when the order is drawn afresh every round: the priority
+ * hash of the round number under the call's seed, H(seed, r). */
+static uint32_t round_seed(uint32_t seed, int32_t r) { return priority(seed, r); }
+
 /* Round-based local max.  Per-round statistics are written for the first
  * `cap` rounds (arrays may be NULL when cap is 0).  max_rounds <= 0 means no
- * limit; otherwise exceeding it returns ORACLE_E_ROUNDS. */
-int oracle_local_max(int32_t n, int32_t m, const int32_t *e_off, const int32_t *e_pins,
-                     const int32_t *v_off, const int32_t *v_edges, const uint32_t *w,
-                     uint32_t seed, int32_t max_rounds, uint32_t *bits, int32_t *rounds_out,
-                     int64_t *live_edges, int64_t *live_pins, int64_t *matched_per_round,
-                     int32_t cap) {
+ * limit; otherwise exceeding it returns ORACLE_E_ROUNDS.  With reseed = 0 the
+ * order is the fixed tuple (w, H(seed, e), e); with reseed = 1 round r ranks
+ * edges by (w, H(H(seed, r), e), e): fresh tie-breaking priorities every
+ * round, as the paper's per-round random weights (Algorithm 1, first phase),
+ * with the weight still deciding first. */
+static int local_max_impl(int32_t n, int32_t m, const int32_t *e_off, const int32_t *e_pins,
+                          const int32_t *v_off, const int32_t *v_edges, const uint32_t *w,
+                          uint32_t seed, int reseed, int32_t max_rounds, uint32_t *bits,
+                          int32_t *rounds_out, int64_t *live_edges, int64_t *live_pins,
+                          int64_t *matched_per_round, int32_t cap) {
     int rc = check_edges(n, m, e_off, e_pins);
     if (rc) return rc;
     if (!v_off || v_off[0] != 0 || v_off[n] != e_off[m]) return ORACLE_E_ARG;
@@ -209,6 +219,10 @@ int oracle_local_max(int32_t n, int32_t m, const int32_t *e_off, const int32_t *
         if (n_live == 0) break;
         if (max_rounds > 0 && round >= max_rounds) { rc = ORACLE_E_ROUNDS; break; }
         if (round < cap) { live_edges[round] = n_live; live_pins[round] = k_live; }
+        if (reseed) {
+            const uint32_t rs = round_seed(seed, round);
+            for (int32_t e = 0; e < m; ++e) rk[e].h = priority(rs, e);
+        }
 
         /* Every active vertex records its best active incident edge (-1: none). */
         for (int32_t v = 0; v < n; ++v) {
@@ -261,6 +275,29 @@ out:
     free(vert_new);
     free(T);
     return rc;
+}
+
+int oracle_local_max(int32_t n, int32_t m, const int32_t *e_off, const int32_t *e_pins,
+                     const int32_t *v_off, const int32_t *v_edges, const uint32_t *w,
+                     uint32_t seed, int32_t max_rounds, uint32_t *bits, int32_t *rounds_out,
+                     int64_t *live_edges, int64_t *live_pins, int64_t *matched_per_round,
+                     int32_t cap) {
+    return local_max_impl(n, m, e_off, e_pins, v_off, v_edges, w, seed, 0, max_rounds, bits,
+                          rounds_out, live_edges, live_pins, matched_per_round, cap);
+}
+
+int oracle_local_max_reseed(int32_t n, int32_t m, const int32_t *e_off, const int32_t *e_pins,
+                            const int32_t *v_off, const int32_t *v_edges, const uint32_t *w,
+                            uint32_t seed, int32_t max_rounds, uint32_t *bits,
+                            int32_t *rounds_out, int64_t *live_edges, int64_t *live_pins,
+                            int64_t *matched_per_round, int32_t cap) {
+    return local_max_impl(n, m, e_off, e_pins, v_off, v_edges, w, seed, 1, max_rounds, bits,
+                          rounds_out, live_edges, live_pins, matched_per_round, cap);
+}
+
+/* Key H(H(seed, r), e) of the reseeded order, for tests. */
+uint32_t oracle_round_priority(uint32_t seed, int32_t round, int32_t e) {
+    return priority(round_seed(seed, round), e);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -305,3 +305,77 @@ def test_round_limit_and_invalid_input():
     bad = g.e_pins.copy(); bad[3] = g.n
     with pytest.raises(ValueError):
         oracle.greedy(g.n, g.m, g.e_off, bad, g.w, 1)
+
+
+# ---------------------------------------------------------------------------
+# Per-round fresh priorities (the paper's re-randomized rounds, weight first)
+
+def test_round_priority_is_murmur_of_round_then_id():
+    for seed in (0, 1, 99):
+        for r in (0, 1, 7):
+            rs = oracle.murmur3_x86_32(int(r).to_bytes(4, "little"), seed)
+            for e in (0, 5, 1000):
+                assert oracle.round_priority(seed, r, e) == oracle.murmur3_x86_32(
+                    int(e).to_bytes(4, "little"), rs)
+
+
+def _lm(g, seed, reseed=True, **kw):
+    return oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed,
+                            reseed=reseed, **kw)
+
+
+def test_reseed_distinct_weights_equals_greedy():
+    """With all weights distinct the tie-breaking priority never decides, so
+    every round's order is the weight order and the result is greedy's."""
+    rng = np.random.default_rng(21)
+    for t in range(200):
+        n = int(rng.integers(2, 60))
+        m = int(rng.integers(1, 80))
+        g = random_instance(300 + t, n, m, 1, 5, 1, 1)
+        g.w = rng.permutation(np.arange(1, m + 1)).astype(np.uint32)   # distinct
+        seed = int(rng.integers(0, 2 ** 32))
+        bg, _, _ = oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, seed)
+        br, st = _lm(g, seed)
+        assert np.array_equal(bg, br), t
+        _stats_invariants(g, br, st)
+
+
+def test_reseed_matching_maximal_and_lemma1():
+    rng = np.random.default_rng(22)
+    for t in range(200):
+        n = int(rng.integers(2, 11))
+        m = int(rng.integers(1, 13))
+        g = random_instance(500 + t, n, m, 1, min(4, n), 1, int(rng.choice([1, 2, 3])))
+        seed = int(rng.integers(0, 2 ** 32))
+        bits, st = _lm(g, seed)
+        assert oracle.check_matching(g.n, g.m, g.e_off, g.e_pins, bits)
+        assert oracle.check_maximal(g.n, g.m, g.e_off, g.e_pins, bits)
+        flags = oracle.bits_to_bool(bits, g.m)
+        wt, cnt = int(g.w[flags].sum()), int(flags.sum())
+        opt_w, opt_c = oracle.brute_force_max(g.n, g.m, g.e_off, g.e_pins, g.w)
+        d = max(int(g.sizes().max()), 1)
+        assert wt * d >= opt_w and cnt * d >= opt_c
+        _stats_invariants(g, bits, st)
+
+
+def test_reseed_round_one_is_fixed_order_with_round_seed():
+    """Round 0 of the reseeded run ranks by H(H(seed, 0), e): its matches are
+    exactly those of a fixed-order run with seed H(seed, 0) in round 0."""
+    g = random_instance(41, 3000, 9000, 2, 6, 1, 3)
+    seed = 12345
+    _, st = _lm(g, seed, cap=4)
+    rs0 = oracle.murmur3_x86_32((0).to_bytes(4, "little"), seed)
+    _, st0 = _lm(g, rs0, reseed=False, cap=4)
+    assert st["matched_per_round"][0] == st0["matched_per_round"][0]
+    assert st["live_edges"][1] == st0["live_edges"][1]
+
+
+def test_reseed_many_small_instances_valid():
+    rng = np.random.default_rng(23)
+    for t in range(500):
+        g = random_instance(900 + t, int(rng.integers(1, 40)), int(rng.integers(0, 60)),
+                            0, 5, 1, int(rng.choice([1, 2, 10])), empty_frac=0.05)
+        bits, st = _lm(g, int(rng.integers(0, 2 ** 32)))
+        assert oracle.check_matching(g.n, g.m, g.e_off, g.e_pins, bits)
+        assert oracle.check_maximal(g.n, g.m, g.e_off, g.e_pins, bits)
+        _stats_invariants(g, bits, st)
