@@ -86,6 +86,14 @@ typedef struct hgm_opts {
                                 and one synchronisation); HGM_E_CSR on failure */
     int32_t max_rounds;      /* > 0: fail with HGM_E_ROUND_LIMIT if live edges
                                 remain after this many rounds; 0 = no limit */
+    int32_t reseed;          /* 0: one order for the whole run, priorities
+                                H(seed, e).  1: priorities drawn afresh every
+                                round, H(H(seed, r), e) in round r, weight still
+                                first (the per-round random weights of
+                                Algorithm 1, first phase).  The result is then
+                                a maximal matching but in general not the
+                                greedy one.  Not with HGM_VARIANT_CREW nor with
+                                hgm_match_batch (HGM_E_ARG). */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */

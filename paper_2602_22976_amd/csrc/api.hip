@@ -24,6 +24,7 @@ constexpr int kEdgeGrid = 2048;  // workgroups of the edge kernels (fixed, devic
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
+    bool stored_keys;  // batch: keys precomputed per instance
     size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, pieces,
         piece_count, hot, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
@@ -40,6 +41,7 @@ void edge_schedule(int64_t m, int *grid, int *region) {
 
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
+    bool reseed;            // priorities redrawn every round (round_seed)
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
     bool have_vertex_side;  // v_off / v_edges given
 };
@@ -51,12 +53,16 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     if (d.variant < HGM_VARIANT_AUTO || d.variant > HGM_VARIANT_CREW) return HGM_E_ARG;
     if (d.hub_threshold < 0 || d.rounds_per_sync < 0 || d.max_rounds < 0) return HGM_E_ARG;
     if (d.rounds_per_sync > kMaxRoundsPerSync) return HGM_E_ARG;
+    if (d.reseed != 0 && d.reseed != 1) return HGM_E_ARG;
+    // The CREW rounds gather a live key stored once for the whole run.
+    if (d.reseed && d.variant == HGM_VARIANT_CREW) return HGM_E_ARG;
     o->variant = d.variant;
     o->hub_threshold = d.hub_threshold ? d.hub_threshold : kDefaultHubThreshold;
     o->adaptive = d.rounds_per_sync == 0;
     o->rounds_per_sync = d.rounds_per_sync ? d.rounds_per_sync : kAdaptiveMaxBatch;
     o->validate = d.validate != 0;
     o->max_rounds = d.max_rounds;
+    o->reseed = d.reseed != 0;
     return HGM_OK;
 }
 
@@ -84,7 +90,8 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     L.ring = o.rounds_per_sync + 2;
     edge_schedule(m, &L.grid, &L.region);
     const size_t cap = (size_t)L.grid * (size_t)L.region;
-    L.key = take(8 * (size_t)m);
+    L.stored_keys = batch;
+    L.key = take(batch ? 8 * (size_t)m : 0);
     L.best0 = take(8 * (size_t)n);
     L.best1 = take(8 * (size_t)n);
     L.done = take((size_t)n);
@@ -118,7 +125,7 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
 State carve(void *ws, const Layout &L, const Opts &o) {
     char *b = (char *)ws;
     State s;
-    s.key = (uint64_t *)(b + L.key);
+    s.key = L.stored_keys ? (uint64_t *)(b + L.key) : nullptr;
     s.best[0] = (uint64_t *)(b + L.best0);
     s.best[1] = (uint64_t *)(b + L.best1);
     s.done = (uint8_t *)(b + L.done);
@@ -183,6 +190,7 @@ int check_batch(const hgm_batch *b, const Opts &o) {
         if (b->kappa_total > 0 && (!b->v_edges || b->n_total == 0)) return HGM_E_ARG;
     }
     if (o.validate) return HGM_E_ARG;  // validate each instance with hgm_match instead
+    if (o.reseed) return HGM_E_ARG;    // per-round seeds are defined for one instance
     return HGM_OK;
 }
 
@@ -298,8 +306,10 @@ struct KernelTimer {
 // rounds; shared by the single-instance and the batched entry point.
 int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s, const Launch &L,
                uint32_t seed, uint32_t *matched_bits, hgm_stats *stats, const BatchIn *batch) {
-    int init_flags = batch ? kInitKeysDone : 0;
+    int init_flags = 0;
     if (uses_live_key(o)) init_flags |= kInitLiveKey;
+    // Priority seed of round r.
+    auto kseed = [&](int r) { return o.reseed ? round_seed(seed, r) : seed; };
     if (any_crew_round(o)) init_flags |= kInitHubs;
     KernelTimer T;
     T.on = stats && stats->timing;
@@ -337,14 +347,14 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     bool finished = g.m == 0;
     if (!finished) {
         if (o.variant == HGM_VARIANT_AUTO && o.have_vertex_side) {
-            HGM_TRY(launch_max0(L, g, s, seed));
+            HGM_TRY(launch_max0(L, g, s, kseed(0)));
             max0_event = (int)T.cls.size();
             HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
         } else if (crew_round(o, 0)) {
-            HGM_TRY(launch_vertex_max(L, g, s, 0, seed));
+            HGM_TRY(launch_vertex_max(L, g, s, 0, kseed(0)));
             HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
         } else {
-            HGM_TRY(launch_scatter(L, g, s));
+            HGM_TRY(launch_scatter(L, g, s, kseed(0)));
             HGM_TRY(T.after(HGM_K_SCATTER, 0));
         }
     }
@@ -359,9 +369,9 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             const bool next_crew = crew_round(o, r + 1);
             // Clear the next round's max buffer when the next round scatters
             // (always in CRCW; at the switch from CREW to CRCW).
-            HGM_TRY(launch_test(L, g, s, r, next_crew ? 0 : 1, matched_bits));
+            HGM_TRY(launch_test(L, g, s, r, next_crew ? 0 : 1, matched_bits, kseed(r)));
             HGM_TRY(T.after(HGM_K_TEST, r));
-            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1));
+            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1)));
             HGM_TRY(T.after(HGM_K_RETIRE, r));
             if (next_crew) {
                 HGM_TRY(launch_vertex_max(L, g, s, r + 1, seed));
@@ -432,7 +442,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
 
 extern "C" {
 
-int hgm_version(void) { return 100; }
+int hgm_version(void) { return 200; }
 
 const char *hgm_strerror(int code) {
     switch (code) {

@@ -13,6 +13,35 @@ constexpr int kSub = 64;     // counters are spread over kSub addresses (one per
 constexpr int kHubPiece = 8192;  // incidences of a hub vertex reduced by one workgroup
 constexpr int kHotDegree = 64;   // vertices at least this degree count as hot (round-0 choice)
 
+__host__ __device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) {
+    return (x << r) | (x >> (32 - r));
+}
+
+// MurmurHash3_x86_32 (Appleby) of the four little-endian bytes of `id`:
+// one body block, no tail, length 4, then the fmix32 finaliser.  Every step
+// is invertible on 32-bit words, so for a fixed seed it is a bijection of id.
+// Edge priorities are H(seed, e); when the order is drawn afresh every round,
+// round r uses the seed H(seed, r) (round_seed).
+__host__ __device__ __forceinline__ uint32_t priority_hash(uint32_t seed, uint32_t id) {
+    uint32_t k = id * 0xcc9e2d51u;
+    k = rotl32(k, 15);
+    k *= 0x1b873593u;
+    uint32_t h = seed ^ k;
+    h = rotl32(h, 13);
+    h = h * 5u + 0xe6546b64u;
+    h ^= 4u;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__host__ __device__ __forceinline__ uint32_t round_seed(uint32_t seed, int round) {
+    return priority_hash(seed, (uint32_t)round);
+}
+
 // Per-round counters, in a small device ring indexed by round % ring.  Every
 // field is split into kSub partial sums (block b adds into entry b % kSub)
 // so that no single address takes one atomic per workgroup; the host sums.
@@ -67,7 +96,8 @@ struct BatchIn {
 // identity.  Compaction is therefore local to a workgroup and needs no
 // global atomic, and an edge stays with the same workgroup for the whole run.
 struct State {
-    uint64_t *key;      // [m] packed key w<<32 | H(seed, e)
+    uint64_t *key;      // [m] batch only: packed key w<<32 | H(seed_i, local id); NULL for
+                        // one instance, whose keys are rebuilt from w and the round's seed
     uint64_t *best[2];  // [n] per-vertex maximum live key, double-buffered by round parity
     uint8_t *done;      // [n] vertex is a pin of a matched edge
     int32_t *list[2];   // [grid * region] live edges per workgroup region
@@ -96,18 +126,20 @@ struct Launch {
 // init_flags: which optional setup k_init performs.
 constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
 constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
-constexpr int kInitKeysDone = 4; // keys were written by k_batch_setup
+// `kseed` arguments: the priority seed of the round the kernel works on
+// (the call's seed, or round_seed(seed, r) when the order is redrawn).
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
                        uint32_t *bits, int init_flags);
 hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
-hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s);
-hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter);
+hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed);
+hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
+                         uint32_t kseed);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
                              uint32_t seed);
 // Round-0 maximum in the form chosen from the degree profile (AUTO).
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed);
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
-                       uint32_t *bits);
+                       uint32_t *bits, uint32_t kseed);
 
 }  // namespace hgm

@@ -5,8 +5,10 @@
 //   test   a live edge e whose key equals best[v] at every pin v is matched;
 //          its pins are marked done
 //   retire every live edge with a done pin leaves the live set (soft delete)
-// Keys are fixed: key(e) = w(e) << 32 | H(seed, e), with H = MurmurHash3_x86_32
-// of e's little-endian bytes; H is a bijection, so keys are distinct.
+// Keys: key(e) = w(e) << 32 | H(seed, e), with H = MurmurHash3_x86_32 of e's
+// little-endian bytes; H is a bijection, so keys are distinct.  The seed is
+// the call's in every round (fixed order), or round_seed(seed, r) in round r
+// when the order is redrawn every round; kernels take it as `kseed`.
 //
 // Work layout.  All kernels are persistent (grid = a few workgroups per CU)
 // and walk their input in chunks of kBlock items (live edges or vertices).
@@ -31,26 +33,13 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
 
-__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) {
-    return (x << r) | (x >> (32 - r));
-}
-
-// MurmurHash3_x86_32 (Appleby) of the four little-endian bytes of `id`:
-// one body block, no tail, length 4, then the fmix32 finaliser.
-__device__ __forceinline__ uint32_t priority_hash(uint32_t seed, uint32_t id) {
-    uint32_t k = id * 0xcc9e2d51u;
-    k = rotl32(k, 15);
-    k *= 0x1b873593u;
-    uint32_t h = seed ^ k;
-    h = rotl32(h, 13);
-    h = h * 5u + 0xe6546b64u;
-    h ^= 4u;
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
+// Key of edge e in a round whose priority seed is kseed.  A batch stores its
+// keys (each instance has its own seed and local ids); one instance rebuilds
+// them from the 4-byte weight, half the bytes of a stored key.
+__device__ __forceinline__ uint64_t edge_key(const Graph &g, const State &s, uint32_t kseed,
+                                             int e) {
+    if (s.key) return s.key[e];
+    return ((uint64_t)g.w[e] << 32) | priority_hash(kseed, (uint32_t)e);
 }
 
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
@@ -180,8 +169,8 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
     if (threadIdx.x < kSub) s.hot[threadIdx.x] = 0;
 }
 
-// Setup: keys, cleared per-vertex state and bitmap; optionally the CREW live
-// keys and the pieces of high-degree vertices.
+// Setup: cleared per-vertex state and bitmap; optionally the CREW live keys
+// and the pieces of high-degree vertices.
 __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s, uint32_t *bits,
                                                  int flags) {
     __shared__ unsigned long long sum_tmp[kWaves];
@@ -191,16 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     const int64_t top = span > words ? span : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
-        if (i < g.m) {
-            uint64_t k;
-            if (flags & kInitKeysDone) {
-                k = s.key[i];
-            } else {
-                k = ((uint64_t)g.w[i] << 32) | priority_hash(seed, (uint32_t)i);
-                s.key[i] = k;
-            }
-            if (flags & kInitLiveKey) s.live_key[i] = k;
-        }
+        if (i < g.m && (flags & kInitLiveKey)) s.live_key[i] = edge_key(g, s, seed, (int)i);
         if (i < g.n) {
             s.best[0][i] = 0;
             s.done[i] = 0;
@@ -288,7 +268,8 @@ __device__ __forceinline__ int region_item(const State &s, int round, int b, int
 // concurrent writes): every edge raises best[pin] to its key at each pin.
 // The plain read first skips the atomic when the slot already holds a larger
 // key; best only grows during the pass, so a stale read is merely cautious.
-__device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b) {
+__device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b,
+                                                uint32_t kseed) {
     uint64_t *best = s.best[0];
     const int cnt = region_count(s, g.m, 0, b);
     for (int c0 = 0; c0 < cnt; c0 += kBlock) {
@@ -300,7 +281,7 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
             const int e = region_item(s, 0, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = s.key[e];
+            key = edge_key(g, s, kseed, e);
             if (g.vbase) vb = g.vbase[e];
         }
         int total;
@@ -315,9 +296,9 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s) {
+__global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t kseed) {
     __shared__ ChunkLds L;
-    scatter0_region(g, s, L, blockIdx.x);
+    scatter0_region(g, s, L, blockIdx.x, kseed);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,7 +312,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s) {
 //   scatter = 1 (CRCW): each survivor raises best[r & 1][pin] at its pins.
 //   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
 //                       vertices' best[r & 1] is cleared for the vertex pass.
-__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter) {
+__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter,
+                                                   uint32_t kseed) {
     __shared__ ChunkLds L;
     const int b = blockIdx.x;
     const int cnt = region_count(s, g.m, round - 1, b);
@@ -357,7 +339,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             e = region_item(s, round - 1, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = s.key[e];
+            key = edge_key(g, s, kseed, e);
             if (g.vbase) vb = g.vbase[e];
         }
         // One lane per edge, stopping at the first done pin: most retired
@@ -415,12 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // later rounds gather live_key (0 once the edge left the live set).
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
                                                uint32_t seed, int e) {
-    if (round == 0) {
-        // A batch's keys depend on each instance's seed and local ids: read them.
-        if (g.vbase) return s.key[e];
-        return ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)e);
-    }
-    return s.live_key[e];
+    return round == 0 ? edge_key(g, s, seed, e) : s.live_key[e];
 }
 
 __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, ChunkLds &L,
@@ -519,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed
     }
     __syncthreads();
     if (edge_form) {
-        if ((int)blockIdx.x < s.grid) scatter0_region(g, s, L, blockIdx.x);
+        if ((int)blockIdx.x < s.grid) scatter0_region(g, s, L, blockIdx.x, seed);
     } else {
         vertex_max_body(g, s, L, 0, seed);
     }
@@ -539,7 +516,7 @@ __global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed
 constexpr int kFullClearRatio = 8;
 
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, int clear_next,
-                                                 uint32_t *bits) {
+                                                 uint32_t *bits, uint32_t kseed) {
     __shared__ ChunkLds L;
     __shared__ int full_clear;
     const int b = blockIdx.x;
@@ -575,7 +552,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             e = region_item(s, round, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = s.key[e];
+            key = edge_key(g, s, kseed, e);
             if (g.vbase) vb = g.vbase[e];
         }
         int matched;
@@ -705,13 +682,15 @@ hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int 
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s) {
-    hipLaunchKernelGGL(k_scatter0, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s);
+hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed) {
+    hipLaunchKernelGGL(k_scatter0, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
     return hipGetLastError();
 }
 
-hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter) {
-    hipLaunchKernelGGL(k_retire, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, scatter);
+hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
+                         uint32_t kseed) {
+    hipLaunchKernelGGL(k_retire, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, scatter,
+                       kseed);
     return hipGetLastError();
 }
 
@@ -728,9 +707,9 @@ hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, in
 }
 
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
-                       uint32_t *bits) {
+                       uint32_t *bits, uint32_t kseed) {
     hipLaunchKernelGGL(k_test, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, clear_next,
-                       bits);
+                       bits, kseed);
     return hipGetLastError();
 }
 

@@ -56,8 +56,12 @@ def test_workspace_size_layout(lib):
     small = hgm.hgm_workspace_size(_csr(10, 20, 100))
     big = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000))
     assert 0 < small < big
-    # keys 8m, two max buffers 16n, done n, two lists 8m at least
-    assert big >= 16 * 5_000_000 + 17 * 2_000_000
+    # two max buffers 16n, done n, two lists 8m at least (keys are rebuilt
+    # from the weights for one instance, not stored)
+    assert big >= 8 * 5_000_000 + 17 * 2_000_000
+    assert big < 8 * 5_000_000 + 17 * 2_000_000 + 8 * 5_000_000
+    rs = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts(reseed=True))
+    assert rs == big
     crew = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts("crew"))
     assert crew > big
     val = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000),
@@ -66,6 +70,11 @@ def test_workspace_size_layout(lib):
     assert hgm.hgm_workspace_size(_csr(-1, 5, 5)) == 0
     assert hgm.hgm_workspace_size(_csr(5, 5, 2 ** 31)) == 0
     assert hgm.hgm_workspace_size(_csr(5, 5, 5), hgm.make_opts(variant=7)) == 0
+    # per-round priorities need the edge-centric rounds
+    assert hgm.hgm_workspace_size(_csr(5, 5, 5), hgm.make_opts("crew", reseed=True)) == 0
+    bad = hgm.make_opts()
+    bad.reseed = 2
+    assert hgm.hgm_workspace_size(_csr(5, 5, 5), bad) == 0
 
 
 def test_match_rejects_bad_arguments_without_gpu(lib):
@@ -90,6 +99,8 @@ def test_match_rejects_bad_arguments_without_gpu(lib):
     st.cap = -1
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, None, 0, st) == hgm.HGM_E_ARG
     o = hgm.make_opts(rounds_per_sync=1000)
+    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
+    o = hgm.make_opts("crew", reseed=True)
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
 
 
@@ -125,6 +136,8 @@ def test_batch_arguments_without_gpu(lib):
     assert hgm.hgm_match_batch(ok, bits, ws, 64) == hgm.HGM_E_SIZE
     assert hgm.hgm_match_batch(ok, 0, ws, 1 << 30) == hgm.HGM_E_ARG
     assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(validate=True)) == hgm.HGM_E_ARG
+    assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(reseed=True)) == hgm.HGM_E_ARG
+    assert hgm.hgm_batch_workspace_size(ok, hgm.make_opts(reseed=True)) == 0
     b = _batch(4, 100, 200, 800, 8)
     b.seeds = None
     assert hgm.hgm_match_batch(b, bits, ws, 1 << 30) == hgm.HGM_E_ARG
