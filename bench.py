@@ -51,18 +51,20 @@ def algorithmic_bytes(stats, variant_rounds, n):
 
     Units per round r: E = live edges, K = their pins, M / P = matched edges
     and their pins, E' / K' = survivors into round r+1.  Counts each array
-    element the step needs once (re-reads from cache are not algorithmic):
-      scatter (round 0): 12 B/edge (offset 4, key 8) + 12 B/pin (pin 4, atomic 8)
-      test:   per edge id 4 (not in round 0) + offsets 8 + key 8, per pin
+    element the step needs once (re-reads from cache are not algorithmic).
+    A key is rebuilt from the 4-byte weight and the hash, never stored:
+      scatter (round 0): 8 B/edge (offset 4, weight 4) + 12 B/pin (pin 4,
+              atomic 8)
+      test:   per edge id 4 (not in round 0) + offsets 8 + weight 4, per pin
               pin 4 + best 8 (+ 8 clearing next round's buffer in CRCW),
               per matched edge 4 (bitmap) and per matched pin 1 (done)
       retire: per edge id 4 (not in round 0) + offsets 8, per pin pin 4 +
-              done 1, per survivor id write 4 (+ key 8 and 8 per surviving
+              done 1, per survivor id write 4 (+ weight 4 and 8 per surviving
               pin for the fused CRCW scatter; CREW: 8 per dead edge key)
       vertex max: per vertex done 1 + offsets 4 + best 8, per pin v_edges 4
-              + weight 4 in round 0 (the key is rebuilt from the weight) or
-              live key 8 in later rounds of the CREW variant (these scan every
-              open vertex's whole list; counted over all pins, an upper bound)
+              + weight 4 in round 0 or live key 8 in later rounds of the CREW
+              variant (these scan every open vertex's whole list; counted
+              over all pins, an upper bound)
     """
     E = list(stats["live_edges"]) + [0]
     K = list(stats["live_pins"]) + [0]
@@ -75,15 +77,15 @@ def algorithmic_bytes(stats, variant_rounds, n):
         crew_next = variant_rounds(r + 1)
         idb = 0 if r == 0 else 4
         if r == 0 and not crew_r:
-            out["scatter"] += 12 * E[0] + 12 * K[0]
+            out["scatter"] += 8 * E[0] + 12 * K[0]
         if crew_r:
             out["vertex_max"] += 13 * n + (8 if r == 0 else 12) * K[0]
-        out["test"] += (idb + 16) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
+        out["test"] += (idb + 12) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
         ret = (idb + 8) * E[r] + 5 * K[r] + 4 * E[r + 1]
         if crew_next:
             ret += 8 * (E[r] - E[r + 1])
         else:
-            ret += 8 * E[r + 1] + 8 * K[r + 1]
+            ret += 4 * E[r + 1] + 8 * K[r + 1]
         out["retire"] += ret
     return out
 
