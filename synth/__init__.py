@@ -5,10 +5,12 @@ module draws random hypergraphs of the shapes the paper evaluates on (sizes,
 degree skew, hub vertices, weight ranges) and lays them out in the dual
 compressed form; it performs none of the matching arithmetic.
 """
-from .gen import (Batch, Hypergraph, batch_from_instances, config_batched,
-                  config_hub_stress, config_plain, config_power_law, config_served_pool,
-                  from_edge_lists, random_instance, transpose)
+from .gen import (Batch, Hypergraph, batch_from_instances, config_batched, config_delaunay,
+                  config_hub_stress, config_plain, config_power_law, config_rgg,
+                  config_served_pool, from_edge_lists, from_pairs, random_instance, rgg_pairs,
+                  transpose)
 
-__all__ = ["Batch", "Hypergraph", "batch_from_instances", "config_batched",
-           "config_hub_stress", "config_plain", "config_power_law", "config_served_pool",
-           "from_edge_lists", "random_instance", "transpose"]
+__all__ = ["Batch", "Hypergraph", "batch_from_instances", "config_batched", "config_delaunay",
+           "config_hub_stress", "config_plain", "config_power_law", "config_rgg",
+           "config_served_pool", "from_edge_lists", "from_pairs", "random_instance", "rgg_pairs",
+           "transpose"]

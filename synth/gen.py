@@ -17,6 +17,13 @@ tens, skewed degrees with hub vertices of up to millions of incidences):
              |e| ~ U{2..12}, w ~ U{1..1000}
   served     requests with kappa ~ log-uniform [1e3, 1e7], |e| ~ U{2..32},
              m = round(kappa/17), n = max(32, round(m/2)), w ~ U{1..1e6}
+  delaunay   graph (every edge 2 pins): Delaunay triangulation of n = 2^20
+             uniform points in the unit square, all w = 1
+  rgg        graph: random geometric graph on n = 2^20 uniform points in the
+             unit square, an edge between points closer than
+             r = 0.55 sqrt(ln n / n) (mean degree about 0.95 ln n), all w = 1
+  Graph vertex ids are the points' generation order (no spatial order); edges
+  are listed by (smaller, larger) endpoint.
 """
 from __future__ import annotations
 
@@ -275,3 +282,78 @@ def poisson_arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
     while t[-1] < duration:
         t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate, size=est))])
     return t[t < duration]
+
+
+# ---------------------------------------------------------------------------
+# Graphs (every edge has exactly two pins), the shapes of the paper's graph
+# experiments (Section 6.3): Delaunay triangulations and random geometric
+# graphs of random points in the unit square, matched with uniform weights.
+
+def from_pairs(n: int, pairs: np.ndarray, w) -> Hypergraph:
+    """Graph from an int64[m, 2] array of distinct endpoints per row."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    m = pairs.shape[0]
+    pins = np.sort(pairs, axis=1).astype(np.int32).reshape(-1)
+    off = (2 * np.arange(m + 1, dtype=np.int64)).astype(np.int32)
+    v_off, v_edges = transpose(n, off, pins)
+    return Hypergraph(n, m, off, pins, v_off, v_edges, np.asarray(w, dtype=np.uint32).reshape(-1))
+
+
+def _unique_pairs(a: np.ndarray, b: np.ndarray, n: int) -> np.ndarray:
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key = np.unique(lo.astype(np.int64) * n + hi)
+    return np.stack([key // n, key % n], axis=1)
+
+
+def config_delaunay(seed: int = 1006, n: int = 1 << 20) -> Hypergraph:
+    """Delaunay triangulation of n uniform random points (unit square)."""
+    from scipy.spatial import Delaunay
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = rng.random((n, 2))
+    tri = Delaunay(pts).simplices.astype(np.int64)
+    a = np.concatenate([tri[:, 0], tri[:, 1], tri[:, 0]])
+    b = np.concatenate([tri[:, 1], tri[:, 2], tri[:, 2]])
+    pairs = _unique_pairs(a, b, n)
+    return from_pairs(n, pairs, np.ones(pairs.shape[0], dtype=np.uint32))
+
+
+def rgg_pairs(pts: np.ndarray, r: float) -> np.ndarray:
+    """All pairs of points closer than r, by a grid of r-sized cells: each
+    point meets the points of its own cell (higher index only) and of four
+    of the eight neighbouring cells, so every close pair is seen once."""
+    n = pts.shape[0]
+    G = max(1, int(math.floor(1.0 / r)))
+    cx = np.minimum((pts[:, 0] * G).astype(np.int64), G - 1)
+    cy = np.minimum((pts[:, 1] * G).astype(np.int64), G - 1)
+    cell = cx * G + cy
+    order = np.argsort(cell, kind="stable")
+    scell = cell[order]
+    start = np.searchsorted(scell, np.arange(G * G + 1))
+    out = []
+    for dx, dy in ((0, 0), (1, -1), (1, 0), (1, 1), (0, 1)):
+        nx, ny = cx[order] + dx, cy[order] + dy
+        ok = (nx >= 0) & (nx < G) & (ny >= 0) & (ny < G)
+        nc = np.where(ok, nx * G + ny, 0)
+        lo = np.where(ok, start[nc], 0)
+        hi = np.where(ok, start[nc + 1], 0)
+        if dx == 0 and dy == 0:
+            lo = np.maximum(lo, np.arange(n) + 1)   # same cell: later points only
+        cnt = np.maximum(hi - lo, 0)
+        src = np.repeat(np.arange(n), cnt)
+        first = np.repeat(lo - np.concatenate([[0], np.cumsum(cnt)[:-1]]), cnt)
+        dst = first + np.arange(cnt.sum())
+        i, j = order[src], order[dst]
+        d2 = ((pts[i] - pts[j]) ** 2).sum(axis=1)
+        keep = d2 < r * r
+        out.append(np.stack([i[keep], j[keep]], axis=1))
+    allp = np.concatenate(out) if out else np.zeros((0, 2), np.int64)
+    return _unique_pairs(allp[:, 0], allp[:, 1], n)
+
+
+def config_rgg(seed: int = 1007, n: int = 1 << 20) -> Hypergraph:
+    """Random geometric graph: n uniform points, r = 0.55 sqrt(ln n / n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = rng.random((n, 2))
+    r = 0.55 * math.sqrt(math.log(n) / n)
+    pairs = rgg_pairs(pts, r)
+    return from_pairs(n, pairs, np.ones(pairs.shape[0], dtype=np.uint32))

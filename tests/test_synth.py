@@ -58,3 +58,37 @@ def test_poisson_arrivals():
     t = synth.gen.poisson_arrivals(1, 2000.0, 5.0)
     assert np.all(np.diff(t) > 0) and t[-1] < 5.0
     assert abs(t.size - 10_000) < 500
+
+
+def test_delaunay_graph_shape():
+    """A Delaunay triangulation of points in general position has
+    3n - 3 - h edges (h = hull vertices, Euler's formula); every edge has two
+    distinct pins and no edge repeats."""
+    from scipy.spatial import ConvexHull
+    n = 3000
+    g = synth.config_delaunay(seed=9, n=n)
+    _well_formed(g, 2, 2)
+    rng = np.random.Generator(np.random.PCG64(9))
+    h = len(ConvexHull(rng.random((n, 2))).vertices)
+    assert g.m == 3 * n - 3 - h
+    pairs = g.e_pins.reshape(-1, 2).astype(np.int64)
+    assert np.unique(pairs[:, 0] * n + pairs[:, 1]).size == g.m
+    assert np.all(g.w == 1)
+
+
+def test_rgg_pairs_brute_force():
+    rng = np.random.Generator(np.random.PCG64(3))
+    pts = rng.random((1500, 2))
+    r = 0.06
+    got = synth.rgg_pairs(pts, r)
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    i, j = np.nonzero(np.triu(d2 < r * r, 1))
+    assert np.array_equal(got, np.stack([i, j], axis=1))
+
+
+def test_rgg_graph_shape():
+    n = 1 << 14
+    g = synth.config_rgg(seed=10, n=n)
+    _well_formed(g, 2, 2)
+    mean_deg = 2 * g.m / n
+    assert abs(mean_deg - 0.95 * np.log(n)) < 1.5   # pi (0.55)^2 ln n, less at the border
