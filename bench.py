@@ -13,6 +13,10 @@ Printed (one JSON line):
                against the 8 TB/s HBM peak; `traffic` from the committed
                rocprofv3 PMC summary when it matches the kernel source
   cpu_baseline the oracle's round simulator on the host (one core), same unit
+  cpu_multicore the OpenMP local max of baselines/ on the host's cores (up
+               to 16 threads), same unit
+  batched / served  the batched-vs-plain and Poisson-served legs
+Graph workloads (delaunay, rgg) run with the pair layout (two pins per edge).
 """
 from __future__ import annotations
 
@@ -35,7 +39,12 @@ WORKLOADS = {
     "hub": ("config_hub_stress", "hub-stress: n=1,000,000, m=4,000,000, |e|~U[2,16], one hub "
             "in 25% of edges, all w=1, seed 1"),
     "plain": ("config_plain", "plain: n=10,000, m=20,000, |e|~U[2,8], w~U[1,1000], seed 1"),
+    "delaunay": ("config_delaunay", "graph, Delaunay triangulation of 2^20 uniform points, "
+                 "m=3,145,692, all w=1, pair layout, seed 1"),
+    "rgg": ("config_rgg", "graph, random geometric graph on 2^20 uniform points, "
+            "r=0.55 sqrt(ln n/n), m=6,891,095, all w=1, pair layout, seed 1"),
 }
+GRAPH_WORKLOADS = {"delaunay", "rgg"}   # every edge has two pins: run with the pair layout
 
 
 def kernel_source_digest() -> str:
@@ -46,13 +55,15 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(stats, variant_rounds, n):
+def algorithmic_bytes(stats, variant_rounds, n, pairs=False):
     """Bytes each kernel class must move, from the per-round counts.
 
     Units per round r: E = live edges, K = their pins, M / P = matched edges
     and their pins, E' / K' = survivors into round r+1.  Counts each array
     element the step needs once (re-reads from cache are not algorithmic).
-    A key is rebuilt from the 4-byte weight and the hash, never stored:
+    A key is rebuilt from the 4-byte weight and the hash, never stored.  With
+    the pair layout (graphs) no edge offsets are read (4 B less per edge in
+    round 0's scatter, 8 B less per edge in every test and retire):
       scatter (round 0): 8 B/edge (offset 4, weight 4) + 12 B/pin (pin 4,
               atomic 8)
       test:   per edge id 4 (not in round 0) + offsets 8 + weight 4, per pin
@@ -61,10 +72,12 @@ def algorithmic_bytes(stats, variant_rounds, n):
       retire: per edge id 4 (not in round 0) + offsets 8, per pin pin 4 +
               done 1, per survivor id write 4 (+ weight 4 and 8 per surviving
               pin for the fused CRCW scatter; CREW: 8 per dead edge key)
-      vertex max: per vertex done 1 + offsets 4 + best 8, per pin v_edges 4
-              + weight 4 in round 0 or live key 8 in later rounds of the CREW
-              variant (these scan every open vertex's whole list; counted
-              over all pins, an upper bound)
+      vertex max: round 0 per vertex done 1 + offsets 4 + best 8, per pin
+              v_edges 4 + weight 4.  Later rounds (CREW variant) read the
+              lists compacted one round earlier: per vertex 21 (adds the list
+              length read and write), per listed incidence id 4 + live key 8
+              (the pins live one round earlier, an upper bound since done
+              vertices are skipped), per kept incidence 4
     """
     E = list(stats["live_edges"]) + [0]
     K = list(stats["live_pins"]) + [0]
@@ -72,16 +85,20 @@ def algorithmic_bytes(stats, variant_rounds, n):
     P = stats["matched_pins"]
     R = stats["rounds"]
     out = {"scatter": 0.0, "test": 0.0, "retire": 0.0, "vertex_max": 0.0}
+    offb = 0 if pairs else 8   # e_off[e], e_off[e + 1] per edge
     for r in range(R):
         crew_r = variant_rounds(r)
         crew_next = variant_rounds(r + 1)
         idb = 0 if r == 0 else 4
         if r == 0 and not crew_r:
-            out["scatter"] += 8 * E[0] + 12 * K[0]
+            out["scatter"] += (offb // 2 + 4) * E[0] + 12 * K[0]
         if crew_r:
-            out["vertex_max"] += 13 * n + (8 if r == 0 else 12) * K[0]
-        out["test"] += (idb + 12) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
-        ret = (idb + 8) * E[r] + 5 * K[r] + 4 * E[r + 1]
+            if r == 0:
+                out["vertex_max"] += 13 * n + 8 * K[0]
+            else:
+                out["vertex_max"] += 21 * n + 12 * K[r - 1] + 4 * K[r]
+        out["test"] += (idb + offb + 4) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
+        ret = (idb + offb) * E[r] + 5 * K[r] + 4 * E[r + 1]
         if crew_next:
             ret += 8 * (E[r] - E[r + 1])
         else:
@@ -277,6 +294,26 @@ def cpu_baseline(g, seed, budget_s):
                        f"oracle greedy on the same input: {tg:.3f} s")}
 
 
+def cpu_multicore(g, seed, budget_s):
+    """The OpenMP local max (baselines/) on the host's cores, full workload."""
+    import baselines
+    threads = max(1, min(16, os.cpu_count() or 1))
+    baselines.local_max(g.n, g.m, g.e_off, g.e_pins, g.w, seed, threads=threads)   # warm-up
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        _, rounds, sum_k = baselines.local_max(g.n, g.m, g.e_off, g.e_pins, g.w, seed,
+                                               threads=threads)
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    t = (time.perf_counter() - t0) / runs
+    return {"value": sum_k / t, "unit": "pin-incidences/s", "cores": threads,
+            "kind": "openmp local max",
+            "sample": (f"multicore CPU local max ({threads} threads) on the full workload, "
+                       f"{runs} run(s) of {t:.3f} s each, {rounds} rounds, sum kappa_r = {sum_k}")}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +324,8 @@ def main():
     ap.add_argument("--rounds-per-sync", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=float, default=10.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-multicore", type=float, default=3.0,
+                    help="seconds of the multicore CPU local max baseline (0 = skip)")
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="instances in the batched-vs-plain leg (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -330,7 +369,12 @@ def main():
     seed = 1
     dev = "cuda:0"
     dg = hgm.DeviceHypergraph.from_host(g, dev)
-    opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync)
+    pairs = args.workload in GRAPH_WORKLOADS
+    if pairs and args.variant == "crew":
+        print("bench.py: graph workloads run the edge-centric rounds (auto or crcw)",
+              file=sys.stderr)
+        sys.exit(2)
+    opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync, pairs=pairs)
     ws = hgm.alloc_workspace(dg, opts)
     bits = torch.empty(max((g.m + 31) // 32, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
@@ -367,7 +411,7 @@ def main():
 
     crew_all = args.variant == "crew"
     crew0 = crew_all or launches.get("vertex_max", 0) > 0   # AUTO's round-0 form
-    model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n)
+    model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n, pairs)
     cand = {k: tot_ms[k] for k in model if tot_ms.get(k, 0) > 0}
     dom = max(cand, key=cand.get)
     dom_ms = tot_ms[dom] / args.steps
@@ -407,6 +451,7 @@ def main():
         "batched": None,
         "served": None,
         "cpu_baseline": None,
+        "cpu_multicore": None,
     }
     if args.batch_count > 0:
         result["batched"] = batched_leg(args.batch_count, max(1, min(args.steps, 5)))
@@ -415,6 +460,8 @@ def main():
                                       args.serve_budget_gb, args.serve_workers)
     if args.cpu_baseline > 0:
         result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
+    if args.cpu_multicore > 0:
+        result["cpu_multicore"] = cpu_multicore(g, seed, args.cpu_multicore)
     print(json.dumps(result), flush=True)
 
 

@@ -94,6 +94,14 @@ typedef struct hgm_opts {
                                 a maximal matching but in general not the
                                 greedy one.  Not with HGM_VARIANT_CREW nor with
                                 hgm_match_batch (HGM_E_ARG). */
+    int32_t pairs;           /* 1: a graph (every edge has exactly two pins,
+                                Section 6.3): the pins of edge e are
+                                e_pins[2e] and e_pins[2e + 1], e_off is not
+                                read (may be NULL), kappa must be 2 m and
+                                e_pins 8-byte aligned (else HGM_E_ARG).  Each
+                                edge is then handled by one lane with one
+                                8-byte pin load.  Not with HGM_VARIANT_CREW
+                                nor with hgm_match_batch (HGM_E_ARG). */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */

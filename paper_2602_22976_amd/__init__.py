@@ -40,7 +40,8 @@ class HgmCsr(ctypes.Structure):
 class HgmOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("max_rounds", ctypes.c_int32), ("reseed", ctypes.c_int32)]
+                ("max_rounds", ctypes.c_int32), ("reseed", ctypes.c_int32),
+                ("pairs", ctypes.c_int32)]
 
 
 class HgmBatch(ctypes.Structure):
@@ -262,7 +263,7 @@ class DeviceBatch:
 
 
 def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False,
-              max_rounds=0, reseed=False) -> HgmOpts:
+              max_rounds=0, reseed=False, pairs=False) -> HgmOpts:
     o = HgmOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.hub_threshold = hub_threshold
@@ -270,6 +271,7 @@ def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False
     o.validate = 1 if validate else 0
     o.max_rounds = max_rounds
     o.reseed = 1 if reseed else 0
+    o.pairs = 1 if pairs else 0
     return o
 
 

@@ -25,7 +25,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
-    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, pieces,
+    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, vedges0,
+        vedges1, vlen0, vlen1, pieces,
         piece_count, hot, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
 };
@@ -42,6 +43,7 @@ void edge_schedule(int64_t m, int *grid, int *region) {
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
     bool reseed;            // priorities redrawn every round (round_seed)
+    bool pairs;             // graph: two pins per edge at e_pins[2e], no offsets
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
     bool have_vertex_side;  // v_off / v_edges given
 };
@@ -56,6 +58,10 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     if (d.reseed != 0 && d.reseed != 1) return HGM_E_ARG;
     // The CREW rounds gather a live key stored once for the whole run.
     if (d.reseed && d.variant == HGM_VARIANT_CREW) return HGM_E_ARG;
+    if (d.pairs != 0 && d.pairs != 1) return HGM_E_ARG;
+    // The pair layout has no edge offsets for the CREW rounds' edge-side passes
+    // to share; graphs run the edge-centric rounds.
+    if (d.pairs && d.variant == HGM_VARIANT_CREW) return HGM_E_ARG;
     o->variant = d.variant;
     o->hub_threshold = d.hub_threshold ? d.hub_threshold : kDefaultHubThreshold;
     o->adaptive = d.rounds_per_sync == 0;
@@ -63,6 +69,7 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     o->validate = d.validate != 0;
     o->max_rounds = d.max_rounds;
     o->reseed = d.reseed != 0;
+    o->pairs = d.pairs != 0;
     return HGM_OK;
 }
 
@@ -102,6 +109,11 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     L.stats = take(sizeof(RoundStats) * (size_t)L.ring);
     L.err = take(4);
     L.live_key = take(uses_live_key(o) ? 8 * (size_t)m : 0);
+    // CREW: incidence lists compacted every round, double-buffered.
+    L.vedges0 = take(uses_live_key(o) ? 4 * (size_t)kappa : 0);
+    L.vedges1 = take(uses_live_key(o) ? 4 * (size_t)kappa : 0);
+    L.vlen0 = take(uses_live_key(o) ? 4 * (size_t)n : 0);
+    L.vlen1 = take(uses_live_key(o) ? 4 * (size_t)n : 0);
     // pieces: each vertex of degree d > T gives ceil(d / P) <= d / P + 1 pieces,
     // and there are fewer than kappa / T such vertices.
     L.piece_cap = any_crew_round(o)
@@ -139,6 +151,11 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.region = L.region;
     s.err = (int32_t *)(b + L.err);
     s.live_key = (uint64_t *)(b + L.live_key);
+    const bool lists = uses_live_key(o);
+    s.vedges[0] = lists ? (int32_t *)(b + L.vedges0) : nullptr;
+    s.vedges[1] = lists ? (int32_t *)(b + L.vedges1) : nullptr;
+    s.vlen[0] = lists ? (int32_t *)(b + L.vlen0) : nullptr;
+    s.vlen[1] = lists ? (int32_t *)(b + L.vlen1) : nullptr;
     s.pieces = (int2 *)(b + L.pieces);
     s.piece_count = (int32_t *)(b + L.piece_count);
     s.hot = (unsigned long long *)(b + L.hot);
@@ -191,6 +208,7 @@ int check_batch(const hgm_batch *b, const Opts &o) {
     }
     if (o.validate) return HGM_E_ARG;  // validate each instance with hgm_match instead
     if (o.reseed) return HGM_E_ARG;    // per-round seeds are defined for one instance
+    if (o.pairs) return HGM_E_ARG;     // batches use the offset layout
     return HGM_OK;
 }
 
@@ -203,7 +221,11 @@ int check_graph(const hgm_csr *g, const Opts &o) {
     if (!g) return HGM_E_ARG;
     if (g->n < 0 || g->m < 0 || g->kappa < 0) return HGM_E_ARG;
     if (g->kappa >= ((int64_t)1 << 31)) return HGM_E_SIZE;
-    if (g->m > 0 && (!g->e_off || !g->w)) return HGM_E_ARG;
+    if (g->m > 0 && ((!o.pairs && !g->e_off) || !g->w)) return HGM_E_ARG;
+    if (o.pairs) {
+        if (g->kappa != 2 * (int64_t)g->m) return HGM_E_ARG;
+        if (((uintptr_t)g->e_pins & 7) != 0) return HGM_E_ARG;  // read as int2
+    }
     if (g->kappa > 0 && !g->e_pins) return HGM_E_ARG;
     if (g->kappa > 0 && g->m == 0) return HGM_E_ARG;
     if (o.variant == HGM_VARIANT_CREW || o.validate) {
@@ -485,7 +507,8 @@ int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     g.m = gin->m;
     g.kappa = gin->kappa;
     g.words = ((int64_t)gin->m + 31) / 32;
-    g.e_off = gin->e_off;
+    g.pairs = o.pairs ? 1 : 0;
+    g.e_off = o.pairs ? nullptr : gin->e_off;
     g.e_pins = gin->e_pins;
     g.v_off = gin->v_off;
     g.v_edges = gin->v_edges;

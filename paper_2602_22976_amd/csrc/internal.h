@@ -63,6 +63,7 @@ struct Graph {
     int32_t n, m;
     int64_t kappa;
     int64_t words;           // bitmap words
+    int32_t pairs;           // every edge has two pins at e_pins[2e], e_pins[2e + 1]; e_off unused
     const int32_t *e_off;
     const int32_t *e_pins;
     const int32_t *v_off;
@@ -113,6 +114,10 @@ struct State {
                         // vertex of degree > hub threshold is cut into kHubPiece pieces
     int32_t *piece_count;  // [1]
     unsigned long long *hot;  // [kSub] incidences on vertices of degree >= kHotDegree
+    int32_t *vedges[2]; // [kappa] live incident edges of each vertex (global ids) at the
+                        // front of its v_off segment, compacted by the vertex pass of
+                        // rounds with parity 0 / 1 (CREW variant)
+    int32_t *vlen[2];   // [n] their counts
     int32_t piece_cap;
     int32_t hub_threshold;
     uint32_t *vbits;    // [ceil(kappa/32)] validation: edge-side incidences seen

@@ -153,6 +153,20 @@ __device__ __forceinline__ void scatter_chunk(const ChunkLds &L, const int32_t *
     }
 }
 
+// Graphs (every edge has two pins, stored as e_pins[2e], e_pins[2e + 1]):
+// one lane per edge reads both pins with one 8-byte load, and no chunk of
+// incidences needs flattening.
+__device__ __forceinline__ int2 pair_pins(const Graph &g, int e) {
+    return reinterpret_cast<const int2 *>(g.e_pins)[e];
+}
+
+__device__ __forceinline__ void scatter_pair(uint64_t *best, int2 p, uint64_t k) {
+    const uint64_t b0 = load_lower_bound(&best[p.x]);
+    const uint64_t b1 = load_lower_bound(&best[p.y]);
+    if (b0 < k) atomic_max_u64(&best[p.x], k);
+    if (b1 < k) atomic_max_u64(&best[p.y], k);
+}
+
 // ---------------------------------------------------------------------------
 // Prologue (one workgroup): round counters, error flag, hub piece counter.
 __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
@@ -162,7 +176,9 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
     __syncthreads();
     if (threadIdx.x == 0) {
         s.stats[0].live[0] = (unsigned long long)g.m;
-        s.stats[0].kappa[0] = g.m > 0 ? (unsigned long long)g.e_off[g.m] : 0ull;
+        s.stats[0].kappa[0] = g.m == 0 ? 0ull
+                              : g.pairs ? 2ull * (unsigned long long)g.m
+                                        : (unsigned long long)g.e_off[g.m];
         *s.err = 0;
         *s.piece_count = 0;
     }
@@ -214,12 +230,14 @@ __global__ void __launch_bounds__(kBlock) k_validate(Graph g, State s, int check
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t kap = g.kappa;
+    // Edge e's pins are e_pins[eoff(e) .. eoff(e + 1)).
+    auto eoff = [&](int64_t e) -> int32_t { return g.pairs ? (int32_t)(2 * e) : g.e_off[e]; };
     if (tid0 == 0) {
-        if (g.m > 0 && (g.e_off[0] != 0 || g.e_off[g.m] != kap)) atomicOr(s.err, 1);
+        if (g.m > 0 && (eoff(0) != 0 || eoff(g.m) != kap)) atomicOr(s.err, 1);
         if (check_dual && (g.v_off[0] != 0 || g.v_off[g.n] != kap)) atomicOr(s.err, 2);
     }
     for (int64_t e = tid0; e < g.m; e += stride) {
-        int32_t a = g.e_off[e], b = g.e_off[e + 1];
+        int32_t a = eoff(e), b = eoff(e + 1);
         if (b < a || a < 0 || b > kap) { atomicOr(s.err, 4); continue; }
         for (int32_t i = a; i < b; ++i) {
             int32_t p = g.e_pins[i];
@@ -235,7 +253,7 @@ __global__ void __launch_bounds__(kBlock) k_validate(Graph g, State s, int check
         for (int32_t i = a; i < b; ++i) {
             int32_t e = g.v_edges[i];
             if (e < 0 || e >= g.m) { atomicOr(s.err, 64); break; }
-            int32_t ea = g.e_off[e], eb = g.e_off[e + 1];
+            int32_t ea = eoff(e), eb = eoff(e + 1);
             if (eb < ea || ea < 0 || eb > kap) { atomicOr(s.err, 64); break; }
             int32_t pos = -1;
             for (int32_t j = ea; j < eb && pos < 0; ++j)
@@ -272,6 +290,13 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
                                                 uint32_t kseed) {
     uint64_t *best = s.best[0];
     const int cnt = region_count(s, g.m, 0, b);
+    if (g.pairs) {
+        for (int i = threadIdx.x; i < cnt; i += kBlock) {
+            const int e = region_item(s, 0, b, i);
+            scatter_pair(best, pair_pins(g, e), edge_key(g, s, kseed, e));
+        }
+        return;
+    }
     for (int c0 = 0; c0 < cnt; c0 += kBlock) {
         const int i = c0 + threadIdx.x;
         int len = 0, base = 0;
@@ -311,7 +336,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 // round's counters.  Then, depending on the variant:
 //   scatter = 1 (CRCW): each survivor raises best[r & 1][pin] at its pins.
 //   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
-//                       vertices' best[r & 1] is cleared for the vertex pass.
+//                       vertices' best[r & 1] and vlen[r & 1] are cleared for
+//                       the vertex pass.
 __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter,
                                                    uint32_t kseed) {
     __shared__ ChunkLds L;
@@ -325,12 +351,36 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         const int np = min(*s.piece_count, s.piece_cap);
         for (int q = threadIdx.x; q < np; q += kBlock) {
             const int2 pc = s.pieces[q];
-            if (pc.y == 0) best[pc.x] = 0;
+            if (pc.y == 0) {
+                best[pc.x] = 0;
+                if (s.vlen[0]) s.vlen[round & 1][pc.x] = 0;
+            }
         }
     }
     int out_pos = 0;                 // survivors written so far (uniform)
     unsigned long long kap_acc = 0;  // their pins (thread 0's copy is the total)
-    for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+    if (g.pairs) {
+        for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+            const int i = c0 + threadIdx.x;
+            int e = -1, alive = 0;
+            int2 p = make_int2(0, 0);
+            if (i < cnt) {
+                e = region_item(s, round - 1, b, i);
+                p = pair_pins(g, e);
+                alive = (s.done[p.x] | s.done[p.y]) ? 0 : 1;
+            }
+            if (!scatter && e >= 0 && !alive) s.live_key[e] = 0;
+            int n_alive;
+            const int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
+            if (alive) {
+                out_list[out_pos + pos] = e;
+                if (scatter) scatter_pair(best, p, edge_key(g, s, kseed, e));
+            }
+            out_pos += n_alive;
+        }
+        kap_acc = 2ull * (unsigned long long)out_pos;
+    }
+    for (int c0 = 0; c0 < cnt && !g.pairs; c0 += kBlock) {
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
@@ -395,6 +445,16 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // Round 0 has no retired edge yet: keys are rebuilt from the weights
 // (w << 32 | H(seed, e)), gathering 4 bytes per incidence instead of 8;
 // later rounds gather live_key (0 once the edge left the live set).
+//
+// Work-optimal lists (Section 5.2.3, the rebuilt incidence arrays): from
+// round 1 on the pass also writes each open vertex's live incident edges to
+// the front of its segment of vedges[r & 1] (same offsets as v_off, any
+// order, global edge ids) with the count in vlen[r & 1], and round r + 1
+// reads those lists instead of the full ones.  A round thus reads only the
+// incidences that were live one round earlier instead of every open vertex's
+// whole list.  Round 1 reads the caller's lists.  Non-hub positions come from
+// an LDS counter per vertex; a hub's from one global atomic per wave on its
+// vlen entry (cleared by the retire pass).
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
                                                uint32_t seed, int e) {
     return round == 0 ? edge_key(g, s, seed, e) : s.live_key[e];
@@ -405,19 +465,45 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
     uint64_t *best = s.best[round & 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int hub_threshold = s.hub_threshold;
+    const bool compact = round >= 1;
+    // Lists read this round: the caller's (local ids in a batch, full degree)
+    // up to round 1, then the ones compacted by the previous round.
+    const bool caller_lists = round <= 1;
+    const int32_t *src = caller_lists ? g.v_edges : s.vedges[(round - 1) & 1];
+    const int32_t *src_len = caller_lists ? nullptr : s.vlen[(round - 1) & 1];
+    int32_t *dst = compact ? s.vedges[round & 1] : nullptr;
+    int32_t *dst_len = compact ? s.vlen[round & 1] : nullptr;
 
     const int n_pieces = min(*s.piece_count, s.piece_cap);
     for (int q = blockIdx.x; q < n_pieces; q += gridDim.x) {
         const int2 pc = s.pieces[q];
         const int v = pc.x;
         if (s.done[v]) continue;
-        const int p0 = g.v_off[v] + pc.y * kHubPiece;
-        const int p1 = min(g.v_off[v + 1], p0 + kHubPiece);
-        const int eb = g.ebase ? g.ebase[v] : 0;
+        const int vo = g.v_off[v];
+        const int len = src_len ? src_len[v] : g.v_off[v + 1] - vo;
+        const int p0 = pc.y * kHubPiece;
+        if (p0 >= len) continue;
+        const int p1 = min(len, p0 + kHubPiece);
+        const int eb = (caller_lists && g.ebase) ? g.ebase[v] : 0;
         uint64_t mx = 0;
-        for (int i = p0 + threadIdx.x; i < p1; i += kBlock) {
-            uint64_t k = vertex_key(g, s, round, seed, g.v_edges[i] + eb);
+        for (int i0 = p0; i0 < p1; i0 += kBlock) {  // uniform trip count (ballot below)
+            const int i = i0 + threadIdx.x;
+            int e = -1;
+            uint64_t k = 0;
+            if (i < p1) {
+                e = src[vo + i] + eb;
+                k = vertex_key(g, s, round, seed, e);
+            }
             mx = k > mx ? k : mx;
+            if (compact) {
+                const bool live = k != 0;
+                const unsigned long long mask = __ballot(live);
+                const int cnt = __popcll(mask);
+                int at = 0;
+                if (lane == 0 && cnt) at = atomicAdd(&dst_len[v], cnt);
+                at = __shfl(at, 0, kWave);
+                if (live) dst[vo + at + __popcll(mask & ((1ull << lane) - 1))] = e;
+            }
         }
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -433,10 +519,9 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         bool own = false;
         if (v < g.n && !s.done[v]) {
             base = g.v_off[v];
-            len = g.v_off[v + 1] - base;
-            own = len <= hub_threshold;
-            if (!own) len = 0;
-            if (g.ebase) eb = g.ebase[v];
+            own = g.v_off[v + 1] - base <= hub_threshold;
+            if (own) len = src_len ? src_len[v] : g.v_off[v + 1] - base;
+            if (caller_lists && g.ebase) eb = g.ebase[v];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
@@ -444,6 +529,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         L.base[threadIdx.x] = base;
         L.key[threadIdx.x] = 0;
         L.vb[threadIdx.x] = eb;
+        L.flag[threadIdx.x] = 0;  // live incidences kept so far
         __syncthreads();
         for (int t0 = 0; t0 < total; t0 += kBlock) {
             const int t = t0 + threadIdx.x;
@@ -451,7 +537,9 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             uint64_t k = 0;
             if (t < total) {
                 j = find_item(L.start, t);
-                k = vertex_key(g, s, round, seed, g.v_edges[L.base[j] + (t - L.start[j])] + L.vb[j]);
+                const int e = src[L.base[j] + (t - L.start[j])] + L.vb[j];
+                k = vertex_key(g, s, round, seed, e);
+                if (compact && k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
             }
             // segmented inclusive max-scan over the wave, segments = equal j
 #pragma unroll
@@ -465,7 +553,10 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             if (j >= 0 && last && k) atomicMax((unsigned long long *)&L.key[j], (unsigned long long)k);
         }
         __syncthreads();
-        if (own) best[v] = L.key[threadIdx.x];
+        if (own) {
+            best[v] = L.key[threadIdx.x];
+            if (compact) dst_len[v] = L.flag[threadIdx.x];
+        }
         __syncthreads();
     }
 }
@@ -543,7 +634,28 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
     }
     const bool clear_pins = clear_next && !full_clear;
     unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
-    for (int c0 = 0; c0 < cnt; c0 += kBlock) {
+    if (g.pairs) {
+        for (int i = threadIdx.x; i < cnt; i += kBlock) {
+            const int e = region_item(s, round, b, i);
+            const int2 p = pair_pins(g, e);
+            const uint64_t key = edge_key(g, s, kseed, e);
+            const uint64_t b0 = best[p.x], b1 = best[p.y];
+            if (clear_pins) {
+                next[p.x] = 0;
+                next[p.y] = 0;
+            }
+            if (b0 == key && b1 == key) {
+                const int bit = g.bitoff ? e + g.bitoff[e] : e;
+                atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+                nm += 1;
+                wm += key >> 32;
+                pm += 2;
+                s.done[p.x] = 1;
+                s.done[p.y] = 1;
+            }
+        }
+    }
+    for (int c0 = 0; c0 < cnt && !g.pairs; c0 += kBlock) {
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;

@@ -102,6 +102,17 @@ def test_match_rejects_bad_arguments_without_gpu(lib):
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
     o = hgm.make_opts("crew", reseed=True)
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
+    # pairs (graphs): kappa must be 2m, e_pins 8-byte aligned, e_off optional
+    assert hgm.hgm_match(_csr(5, 5, 9), 1, bits, ws, 1 << 30,
+                         hgm.make_opts(pairs=True)) == hgm.HGM_E_ARG
+    c = _csr(5, 5, 10)
+    c.e_pins = 0x1004
+    assert hgm.hgm_match(c, 1, bits, ws, 1 << 30, hgm.make_opts(pairs=True)) == hgm.HGM_E_ARG
+    assert hgm.hgm_match(_csr(5, 5, 10), 1, bits, ws, 1 << 30,
+                         hgm.make_opts("crew", pairs=True)) == hgm.HGM_E_ARG
+    bad = hgm.make_opts()
+    bad.pairs = 3
+    assert hgm.hgm_match(_csr(5, 5, 10), 1, bits, ws, 1 << 30, bad) == hgm.HGM_E_ARG
 
 
 def test_product_package_does_not_use_the_oracle():
@@ -111,6 +122,7 @@ def test_product_package_does_not_use_the_oracle():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "import baselines" not in text and "from baselines" not in text, fn
                 assert "oracle_" not in text, fn
 
 
@@ -138,6 +150,7 @@ def test_batch_arguments_without_gpu(lib):
     assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(validate=True)) == hgm.HGM_E_ARG
     assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(reseed=True)) == hgm.HGM_E_ARG
     assert hgm.hgm_batch_workspace_size(ok, hgm.make_opts(reseed=True)) == 0
+    assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(pairs=True)) == hgm.HGM_E_ARG
     b = _batch(4, 100, 200, 800, 8)
     b.seeds = None
     assert hgm.hgm_match_batch(b, bits, ws, 1 << 30) == hgm.HGM_E_ARG

@@ -153,6 +153,31 @@ def test_crew_hub_split(hgm, threshold):
     _check(hgm, g, 1, "crew", hub_threshold=threshold)
 
 
+def _hub_on_path(path_edges=201, hub_edges=20_000, seed=5):
+    """A path with increasing weights (one match every two rounds from the top
+    end) and a hub whose lighter 3-pin edges {hub, leaf, path vertex} die as
+    their path vertex is matched: the hub stays open for ~100 rounds while its
+    live list shrinks every round."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_path = path_edges + 1
+    hub = n_path
+    edges = [[i, i + 1] for i in range(path_edges)]
+    w = list(1000 + np.arange(path_edges))
+    on = rng.integers(0, n_path, size=hub_edges)
+    for k in range(hub_edges):
+        edges.append([hub, hub + 1 + k, int(on[k])])
+    w += list(rng.integers(1, 1000, size=hub_edges))
+    return synth.from_edge_lists(hub + 1 + hub_edges, edges, np.array(w))
+
+
+@pytest.mark.parametrize("threshold", [4, 64, 100_000])
+def test_crew_list_compaction_many_rounds(hgm, threshold):
+    g = _hub_on_path()
+    print(f"hub on path threshold={threshold}", flush=True)
+    st = _check(hgm, g, 3, "crew", hub_threshold=threshold, max_rounds=1000)
+    assert st["rounds"] >= 100
+
+
 def test_round_limit(hgm):
     import torch
     g = path_graph(40)
