@@ -392,18 +392,46 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             key = edge_key(g, s, kseed, e);
             if (g.vbase) vb = g.vbase[e];
         }
-        // One lane per edge, stopping at the first done pin: most retired
-        // edges are found after one or two reads, survivors read all pins.
+        // The first kUnroll pins one lane per edge: most retired edges are
+        // found there, and most edges have no more pins.  The pins beyond
+        // them, of the edges still undecided, are spread over all lanes of
+        // the workgroup, kUnroll per lane and step, so that a long
+        // surviving edge does not hold its wave for a chain of reads.
         bool dead = false;
-        for (int k0 = 0; k0 < len && !dead; k0 += kUnroll) {
+        {
             int p[kUnroll];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] + vb : -1;
+            for (int u = 0; u < kUnroll; ++u) p[u] = u < len ? g.e_pins[base + u] + vb : -1;
             uint8_t dv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) dv[u] = p[u] >= 0 ? s.done[p[u]] : 0;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) dead |= dv[u] != 0;
+        }
+        {
+            const int rest = (e >= 0 && !dead && len > kUnroll) ? len - kUnroll : 0;
+            int total_r;
+            const int st_r = block_exclusive_sum(rest, L.wave_tmp, &total_r);
+            if (total_r > 0) {
+                L.start[threadIdx.x] = st_r;
+                L.base[threadIdx.x] = base + kUnroll;
+                L.vb[threadIdx.x] = vb;
+                L.flag[threadIdx.x] = 0;
+                __syncthreads();
+                for (int t0 = threadIdx.x; t0 < total_r; t0 += kUnroll * kBlock) {
+                    int jj[kUnroll], pin[kUnroll];
+                    chunk_pins(L, g.e_pins, total_r, t0, jj, pin);
+                    uint8_t dv[kUnroll];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) dv[u] = jj[u] >= 0 ? s.done[pin[u]] : 0;
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (dv[u]) L.flag[jj[u]] = 1;
+                }
+                __syncthreads();
+                dead = dead || L.flag[threadIdx.x];
+                __syncthreads();
+            }
         }
         const int alive = (e >= 0 && len > 0 && !dead) ? 1 : 0;
         L.base[threadIdx.x] = base;
@@ -460,15 +488,17 @@ __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, i
     return round == 0 ? edge_key(g, s, seed, e) : s.live_key[e];
 }
 
+// kCompact: rounds >= 1 (list compaction); round 0 instantiates without it.
+template <bool kCompact>
 __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, ChunkLds &L,
                                                 int round, uint32_t seed) {
     uint64_t *best = s.best[round & 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int hub_threshold = s.hub_threshold;
-    const bool compact = round >= 1;
+    constexpr bool compact = kCompact;
     // Lists read this round: the caller's (local ids in a batch, full degree)
     // up to round 1, then the ones compacted by the previous round.
-    const bool caller_lists = round <= 1;
+    const bool caller_lists = !kCompact || round <= 1;
     const int32_t *src = caller_lists ? g.v_edges : s.vedges[(round - 1) & 1];
     const int32_t *src_len = caller_lists ? nullptr : s.vlen[(round - 1) & 1];
     int32_t *dst = compact ? s.vedges[round & 1] : nullptr;
@@ -495,7 +525,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
                 k = vertex_key(g, s, round, seed, e);
             }
             mx = k > mx ? k : mx;
-            if (compact) {
+            if constexpr (compact) {
                 const bool live = k != 0;
                 const unsigned long long mask = __ballot(live);
                 const int cnt = __popcll(mask);
@@ -539,7 +569,9 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
                 j = find_item(L.start, t);
                 const int e = src[L.base[j] + (t - L.start[j])] + L.vb[j];
                 k = vertex_key(g, s, round, seed, e);
-                if (compact && k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
+                if constexpr (compact) {
+                    if (k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
+                }
             }
             // segmented inclusive max-scan over the wave, segments = equal j
 #pragma unroll
@@ -555,7 +587,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         __syncthreads();
         if (own) {
             best[v] = L.key[threadIdx.x];
-            if (compact) dst_len[v] = L.flag[threadIdx.x];
+            if constexpr (compact) dst_len[v] = L.flag[threadIdx.x];
         }
         __syncthreads();
     }
@@ -563,7 +595,10 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
 
 __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, uint32_t seed) {
     __shared__ ChunkLds L;
-    vertex_max_body(g, s, L, round, seed);
+    if (round == 0)
+        vertex_max_body<false>(g, s, L, round, seed);
+    else
+        vertex_max_body<true>(g, s, L, round, seed);
 }
 
 // Round-0 maximum when the library chooses the form (AUTO).  The edge-centric
@@ -589,7 +624,7 @@ __global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed
     if (edge_form) {
         if ((int)blockIdx.x < s.grid) scatter0_region(g, s, L, blockIdx.x, seed);
     } else {
-        vertex_max_body(g, s, L, 0, seed);
+        vertex_max_body<false>(g, s, L, 0, seed);
     }
 }
 
@@ -605,6 +640,7 @@ __global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed
 // of this round's live edges, so the next scatter starts from zero at all of
 // its pins.  Workgroup 0 also clears the counters of round r+1.
 constexpr int kFullClearRatio = 8;
+constexpr int kTestEdges = 2;  // edges per lane and step of the early-exit test
 
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, int clear_next,
                                                  uint32_t *bits, uint32_t kseed) {
@@ -655,7 +691,65 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             }
         }
     }
-    for (int c0 = 0; c0 < cnt && !g.pairs; c0 += kBlock) {
+    // A matched edge sets its bit and marks its pins (no other live edge
+    // shares a pin with it in this round).
+    auto record = [&](int e, int base, int len, int vb, uint64_t key) {
+        const int bit = g.bitoff ? e + g.bitoff[e] : e;
+        atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+        nm += 1;
+        wm += key >> 32;
+        pm += (unsigned long long)len;
+        for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k] + vb] = 1;
+    };
+    if (!g.pairs && !clear_pins) {
+        // One lane per edge, stopping at the first pin where the edge is not
+        // the maximum: almost every edge fails at its first pin.  A lane
+        // takes kTestEdges edges per step with their loads issued together,
+        // so their dependent chains (id, offsets, pin, maximum) overlap.
+        for (int c0 = 0; c0 < cnt; c0 += kTestEdges * kBlock) {
+            int e[kTestEdges], len[kTestEdges], base[kTestEdges], vb[kTestEdges];
+            uint64_t key[kTestEdges];
+            bool ok[kTestEdges];
+#pragma unroll
+            for (int u = 0; u < kTestEdges; ++u) {
+                const int i = c0 + u * kBlock + threadIdx.x;
+                e[u] = i < cnt ? region_item(s, round, b, i) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kTestEdges; ++u) {
+                len[u] = base[u] = vb[u] = 0;
+                key[u] = 0;
+                if (e[u] >= 0) {
+                    base[u] = g.e_off[e[u]];
+                    len[u] = g.e_off[e[u] + 1] - base[u];
+                    key[u] = edge_key(g, s, kseed, e[u]);
+                    if (g.vbase) vb[u] = g.vbase[e[u]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kTestEdges; ++u)
+                ok[u] = e[u] >= 0 && (len[u] == 0 || best[g.e_pins[base[u]] + vb[u]] == key[u]);
+#pragma unroll
+            for (int u = 0; u < kTestEdges; ++u) {
+                // the rest of the pins, kUnroll at a time, while still the maximum
+                for (int k0 = 1; k0 < len[u] && ok[u]; k0 += kUnroll) {
+                    int p[kUnroll];
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q)
+                        p[q] = k0 + q < len[u] ? g.e_pins[base[u] + k0 + q] + vb[u] : -1;
+                    uint64_t bv[kUnroll];
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q) bv[q] = p[q] >= 0 ? best[p[q]] : key[u];
+#pragma unroll
+                    for (int q = 0; q < kUnroll; ++q) ok[u] = ok[u] && bv[q] == key[u];
+                }
+                if (ok[u]) record(e[u], base[u], len[u], vb[u], key[u]);
+            }
+        }
+    }
+    for (int c0 = 0; c0 < cnt && !g.pairs && clear_pins; c0 += kBlock) {
+        // Every pin is visited (its next-round entry is cleared), spread over
+        // the lanes.
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
@@ -667,59 +761,31 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             key = edge_key(g, s, kseed, e);
             if (g.vbase) vb = g.vbase[e];
         }
-        int matched;
-        if (!clear_pins) {
-            // One lane per edge, stopping at the first pin where the edge is
-            // not the maximum: almost every edge fails at its first pin.
-            // The first pin alone, then the rest kUnroll at a time.
-            bool ok = e >= 0 && (len == 0 || best[g.e_pins[base] + vb] == key);
-            for (int k0 = 1; k0 < len && ok; k0 += kUnroll) {
-                int p[kUnroll];
+        int total;
+        int st = block_exclusive_sum(len, L.wave_tmp, &total);
+        L.start[threadIdx.x] = st;
+        L.base[threadIdx.x] = base;
+        L.key[threadIdx.x] = key;
+        L.flag[threadIdx.x] = 0;
+        L.vb[threadIdx.x] = vb;
+        __syncthreads();
+        for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
+            int j[kUnroll], pin[kUnroll];
+            chunk_pins(L, g.e_pins, total, t0, j, pin);
+            uint64_t bv[kUnroll];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? g.e_pins[base + k0 + u] + vb : -1;
-                uint64_t bv[kUnroll];
+            for (int u = 0; u < kUnroll; ++u) bv[u] = j[u] >= 0 ? best[pin[u]] : 0;
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) bv[u] = p[u] >= 0 ? best[p[u]] : key;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) ok = ok && bv[u] == key;
+            for (int u = 0; u < kUnroll; ++u) {
+                if (j[u] < 0) continue;
+                if (bv[u] != L.key[j[u]]) L.flag[j[u]] = 1;
+                next[pin[u]] = 0;
             }
-            matched = ok ? 1 : 0;
-        } else {
-            // Every pin is visited (its next-round entry is cleared), spread
-            // over the lanes.
-            int total;
-            int st = block_exclusive_sum(len, L.wave_tmp, &total);
-            L.start[threadIdx.x] = st;
-            L.base[threadIdx.x] = base;
-            L.key[threadIdx.x] = key;
-            L.flag[threadIdx.x] = 0;
-            L.vb[threadIdx.x] = vb;
-            __syncthreads();
-            for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
-                int j[kUnroll], pin[kUnroll];
-                chunk_pins(L, g.e_pins, total, t0, j, pin);
-                uint64_t bv[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) bv[u] = j[u] >= 0 ? best[pin[u]] : 0;
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (j[u] < 0) continue;
-                    if (bv[u] != L.key[j[u]]) L.flag[j[u]] = 1;
-                    next[pin[u]] = 0;
-                }
-            }
-            __syncthreads();
-            matched = (e >= 0 && !L.flag[threadIdx.x]) ? 1 : 0;
-            __syncthreads();
         }
-        if (matched) {
-            const int bit = g.bitoff ? e + g.bitoff[e] : e;
-            atomicOr(&bits[bit >> 5], 1u << (bit & 31));
-            nm += 1;
-            wm += key >> 32;
-            pm += (unsigned long long)len;
-            for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k] + vb] = 1;
-        }
+        __syncthreads();
+        const bool matched = e >= 0 && !L.flag[threadIdx.x];
+        __syncthreads();
+        if (matched) record(e, base, len, vb, key);
     }
     nm = block_sum_u64(nm, L.sum_tmp);
     wm = block_sum_u64(wm, L.sum_tmp);

@@ -153,6 +153,20 @@ def test_crew_hub_split(hgm, threshold):
     _check(hgm, g, 1, "crew", hub_threshold=threshold)
 
 
+@pytest.mark.parametrize("threshold", [1, 4, 64, 100_000])
+def test_auto_vertex_form_hub_split(hgm, threshold):
+    """AUTO on a degree profile without many hot incidences takes the
+    vertex-centric round 0, whose hub pieces depend on the threshold."""
+    g = synth.config_hub_stress(seed=22, n=50_000, m=40_000)   # non-hub degree ~7
+    print(f"auto vertex form threshold={threshold}", flush=True)
+    _check(hgm, g, 2, "auto", hub_threshold=threshold)
+    import torch
+    dg = hgm.DeviceHypergraph.from_host(g, "cuda:0")
+    _, st = hgm.match(dg, 2, hgm.make_opts("auto", hub_threshold=threshold), timing=True)
+    torch.cuda.synchronize()
+    assert st["kernel_launches"]["vertex_max"] == 1 and st["kernel_launches"]["scatter"] == 0
+
+
 def _hub_on_path(path_edges=201, hub_edges=20_000, seed=5):
     """A path with increasing weights (one match every two rounds from the top
     end) and a hub whose lighter 3-pin edges {hub, leaf, path vertex} die as
