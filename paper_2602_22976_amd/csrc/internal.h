@@ -142,7 +142,8 @@ hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int ro
                          uint32_t kseed);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
                              uint32_t seed);
-// Round-0 maximum in the form chosen from the degree profile (AUTO).
+// Round-0 maximum in the form chosen from the degree profile (AUTO): two
+// launches, of which the one not chosen returns at once.
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed);
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
                        uint32_t *bits, uint32_t kseed);

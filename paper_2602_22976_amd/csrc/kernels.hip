@@ -153,6 +153,73 @@ __device__ __forceinline__ void scatter_chunk(const ChunkLds &L, const int32_t *
     }
 }
 
+// Per-workgroup table of hub vertices (degree above the hub threshold, as
+// listed by the hub pieces) for the round-0 edge scatter.  Every workgroup
+// meets the few hubs in a large share of its incidences, and device atomics
+// on one address serialise, so a hub's pins are reduced in LDS for the
+// workgroup's whole region and pushed to best[] once at the end.  Open
+// addressing with linear probing; at most half the slots are filled, so a
+// probe always reaches the hub or an empty slot.
+constexpr int kHubSlotBits = 10;
+constexpr int kHubSlots = 1 << kHubSlotBits;
+constexpr int kHubTableMax = kHubSlots / 2;
+
+struct HubTable {
+    int id[kHubSlots];                 // hub vertex, -1 = empty
+    unsigned long long mx[kHubSlots];  // the workgroup's largest key at that hub
+    int count;
+};
+
+__device__ __forceinline__ int hub_home(int v) {
+    return (int)(((uint32_t)v * 0x9E3779B1u) >> (32 - kHubSlotBits));
+}
+
+// Slot of v, or -1 when v is not in the table.
+__device__ __forceinline__ int hub_find(const HubTable &H, int v) {
+    int h = hub_home(v);
+    for (;;) {
+        const int id = H.id[h];
+        if (id == v) return h;
+        if (id < 0) return -1;
+        h = (h + 1) & (kHubSlots - 1);
+    }
+}
+
+// Fills the table from the hub pieces (one piece with index 0 per hub).
+// Hubs beyond kHubTableMax stay out and take the global path.
+__device__ void hub_table_build(HubTable &H, const State &s) {
+    for (int i = threadIdx.x; i < kHubSlots; i += kBlock) {
+        H.id[i] = -1;
+        H.mx[i] = 0;
+    }
+    if (threadIdx.x == 0) H.count = 0;
+    __syncthreads();
+    const int np = min(*s.piece_count, s.piece_cap);
+    for (int q = threadIdx.x; q < np; q += kBlock) {
+        const int2 pc = s.pieces[q];
+        if (pc.y != 0 || atomicAdd(&H.count, 1) >= kHubTableMax) continue;
+        int h = hub_home(pc.x);
+        while (atomicCAS(&H.id[h], -1, pc.x) != -1) h = (h + 1) & (kHubSlots - 1);
+    }
+    __syncthreads();
+}
+
+// scatter_chunk with hub pins reduced in the table.
+__device__ __forceinline__ void scatter_chunk_hubs(const ChunkLds &L, const int32_t *e_pins,
+                                                   int total, uint64_t *best, HubTable &H) {
+    for (int t = threadIdx.x; t < total; t += kBlock) {
+        const int j = find_item(L.start, t);
+        const int pin = e_pins[L.base[j] + (t - L.start[j])] + L.vb[j];
+        const uint64_t k = L.key[j];
+        const int h = hub_find(H, pin);
+        if (h >= 0) {
+            if (H.mx[h] < k) atomicMax(&H.mx[h], (unsigned long long)k);
+        } else if (load_lower_bound(&best[pin]) < k) {
+            atomic_max_u64(&best[pin], k);
+        }
+    }
+}
+
 // Graphs (every edge has two pins, stored as e_pins[2e], e_pins[2e + 1]):
 // one lane per edge reads both pins with one 8-byte load, and no chunk of
 // incidences needs flattening.
@@ -286,8 +353,10 @@ __device__ __forceinline__ int region_item(const State &s, int round, int b, int
 // concurrent writes): every edge raises best[pin] to its key at each pin.
 // The plain read first skips the atomic when the slot already holds a larger
 // key; best only grows during the pass, so a stale read is merely cautious.
+// With a hub table H (AUTO's round 0), hub pins are reduced in LDS and
+// pushed once per workgroup at the end.
 __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b,
-                                                uint32_t kseed) {
+                                                uint32_t kseed, HubTable *H = nullptr) {
     uint64_t *best = s.best[0];
     const int cnt = region_count(s, g.m, 0, b);
     if (g.pairs) {
@@ -316,8 +385,18 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
         L.key[threadIdx.x] = key;
         L.vb[threadIdx.x] = vb;
         __syncthreads();
-        scatter_chunk(L, g.e_pins, total, best);
+        if (H)
+            scatter_chunk_hubs(L, g.e_pins, total, best, *H);
+        else
+            scatter_chunk(L, g.e_pins, total, best);
         __syncthreads();
+    }
+    if (H) {
+        for (int i = threadIdx.x; i < kHubSlots; i += kBlock) {
+            const int v = H->id[i];
+            const uint64_t k = H->mx[i];
+            if (v >= 0 && k && load_lower_bound(&best[v]) < k) atomic_max_u64(&best[v], k);
+        }
     }
 }
 
@@ -608,24 +687,37 @@ __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int rou
 // weight per incidence with no atomics, which is faster when incidences are
 // spread evenly.  k_init counted the incidences of vertices of degree >=
 // kHotDegree; the edge form is taken when they are at least half of all.
-__global__ void __launch_bounds__(kBlock) k_max0(Graph g, State s, uint32_t seed) {
-    __shared__ ChunkLds L;
+// The edge form reduces the hubs' pins in each workgroup's hub table.
+// Two kernels, each running only when the form is its own: the edge form
+// with its hub table and the vertex form are compiled separately (one kernel
+// holding both ran the vertex form 7% slower).  Both read the form from the
+// degree profile on the device, so the host needs no synchronisation.
+__device__ __forceinline__ bool max0_edge_form(const Graph &g, const State &s) {
     __shared__ int edge_form;
     if (threadIdx.x < kWave) {
         unsigned long long hot = s.hot[threadIdx.x];
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) hot += __shfl_xor(hot, o, kWave);
-        if (threadIdx.x == 0) {
-            edge_form = 2 * hot >= (unsigned long long)g.kappa;
-            if (blockIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
-        }
+        if (threadIdx.x == 0) edge_form = 2 * hot >= (unsigned long long)g.kappa;
     }
     __syncthreads();
-    if (edge_form) {
-        if ((int)blockIdx.x < s.grid) scatter0_region(g, s, L, blockIdx.x, seed);
-    } else {
-        vertex_max_body<false>(g, s, L, 0, seed);
-    }
+    return edge_form != 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t seed) {
+    __shared__ ChunkLds L;
+    __shared__ HubTable H;
+    const bool edge_form = max0_edge_form(g, s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
+    if (!edge_form) return;
+    hub_table_build(H, s);
+    scatter0_region(g, s, L, blockIdx.x, seed, &H);
+}
+
+__global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32_t seed) {
+    __shared__ ChunkLds L;
+    if (max0_edge_form(g, s)) return;
+    vertex_max_body<false>(g, s, L, 0, seed);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,8 +965,8 @@ hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int ro
 }
 
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed) {
-    const int grid = L.grid > s.grid ? L.grid : s.grid;
-    hipLaunchKernelGGL(k_max0, dim3(grid), dim3(kBlock), 0, L.stream, g, s, seed);
+    hipLaunchKernelGGL(k_max0_edge, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
+    hipLaunchKernelGGL(k_max0_vertex, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, seed);
     return hipGetLastError();
 }
 
