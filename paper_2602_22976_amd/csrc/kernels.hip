@@ -355,11 +355,12 @@ __device__ __forceinline__ int region_item(const State &s, int round, int b, int
 // key; best only grows during the pass, so a stale read is merely cautious.
 // With a hub table H (AUTO's round 0), hub pins are reduced in LDS and
 // pushed once per workgroup at the end.
+template <bool kPairs>
 __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b,
                                                 uint32_t kseed, HubTable *H = nullptr) {
     uint64_t *best = s.best[0];
     const int cnt = region_count(s, g.m, 0, b);
-    if (g.pairs) {
+    if constexpr (kPairs) {
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
             const int e = region_item(s, 0, b, i);
             scatter_pair(best, pair_pins(g, e), edge_key(g, s, kseed, e));
@@ -400,9 +401,10 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
     }
 }
 
+template <bool kPairs>
 __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t kseed) {
     __shared__ ChunkLds L;
-    scatter0_region(g, s, L, blockIdx.x, kseed);
+    scatter0_region<kPairs>(g, s, L, blockIdx.x, kseed);
 }
 
 // ---------------------------------------------------------------------------
@@ -417,8 +419,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 //   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
 //                       vertices' best[r & 1] and vlen[r & 1] are cleared for
 //                       the vertex pass.
-__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, int scatter,
-                                                   uint32_t kseed) {
+// kPairs: graph layout; kScatter: the CRCW form (else CREW).  Each
+// combination is its own kernel: a kernel holding every path runs the hot
+// one slower.
+template <bool kPairs, bool kScatter>
+__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed) {
+    constexpr bool scatter = kScatter;
     __shared__ ChunkLds L;
     const int b = blockIdx.x;
     const int cnt = region_count(s, g.m, round - 1, b);
@@ -426,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
     uint64_t *best = s.best[round & 1];
     RoundStats *st_out = &s.stats[round % s.ring];
 
-    if (!scatter && b == 0) {
+    if (!kScatter && b == 0) {
         const int np = min(*s.piece_count, s.piece_cap);
         for (int q = threadIdx.x; q < np; q += kBlock) {
             const int2 pc = s.pieces[q];
@@ -438,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
     }
     int out_pos = 0;                 // survivors written so far (uniform)
     unsigned long long kap_acc = 0;  // their pins (thread 0's copy is the total)
-    if (g.pairs) {
+    if constexpr (kPairs) {
         for (int c0 = 0; c0 < cnt; c0 += kBlock) {
             const int i = c0 + threadIdx.x;
             int e = -1, alive = 0;
@@ -459,7 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         }
         kap_acc = 2ull * (unsigned long long)out_pos;
     }
-    for (int c0 = 0; c0 < cnt && !g.pairs; c0 += kBlock) {
+    for (int c0 = 0; c0 < cnt && !kPairs; c0 += kBlock) {
         const int i = c0 + threadIdx.x;
         int e = -1, len = 0, base = 0;
         uint64_t key = 0;
@@ -704,6 +710,7 @@ __device__ __forceinline__ bool max0_edge_form(const Graph &g, const State &s) {
     return edge_form != 0;
 }
 
+template <bool kPairs>
 __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t seed) {
     __shared__ ChunkLds L;
     __shared__ HubTable H;
@@ -711,7 +718,7 @@ __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
     if (!edge_form) return;
     hub_table_build(H, s);
-    scatter0_region(g, s, L, blockIdx.x, seed, &H);
+    scatter0_region<kPairs>(g, s, L, blockIdx.x, seed, &H);
 }
 
 __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32_t seed) {
@@ -734,6 +741,8 @@ __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32
 constexpr int kFullClearRatio = 8;
 constexpr int kTestEdges = 2;  // edges per lane and step of the early-exit test
 
+// kPairs: graph layout (instantiated separately; g.pairs equals it).
+template <bool kPairs>
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, int clear_next,
                                                  uint32_t *bits, uint32_t kseed) {
     __shared__ ChunkLds L;
@@ -762,7 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
     }
     const bool clear_pins = clear_next && !full_clear;
     unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
-    if (g.pairs) {
+    if constexpr (kPairs) {
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
             const int e = region_item(s, round, b, i);
             const int2 p = pair_pins(g, e);
@@ -793,7 +802,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
         pm += (unsigned long long)len;
         for (int k = 0; k < len; ++k) s.done[g.e_pins[base + k] + vb] = 1;
     };
-    if (!g.pairs && !clear_pins) {
+    if (!kPairs && !clear_pins) {
         // One lane per edge, stopping at the first pin where the edge is not
         // the maximum: almost every edge fails at its first pin.  A lane
         // takes kTestEdges edges per step with their loads issued together,
@@ -839,7 +848,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             }
         }
     }
-    for (int c0 = 0; c0 < cnt && !g.pairs && clear_pins; c0 += kBlock) {
+    for (int c0 = 0; c0 < cnt && !kPairs && clear_pins; c0 += kBlock) {
         // Every pin is visited (its next-round entry is cleared), spread over
         // the lanes.
         const int i = c0 + threadIdx.x;
@@ -953,19 +962,32 @@ hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int 
 }
 
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed) {
-    hipLaunchKernelGGL(k_scatter0, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
+    if (g.pairs)
+        hipLaunchKernelGGL(k_scatter0<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
+    else
+        hipLaunchKernelGGL(k_scatter0<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
     return hipGetLastError();
 }
 
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
                          uint32_t kseed) {
-    hipLaunchKernelGGL(k_retire, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, scatter,
-                       kseed);
+    const dim3 grid(s.grid), block(kBlock);
+    if (g.pairs && scatter)
+        hipLaunchKernelGGL((k_retire<true, true>), grid, block, 0, L.stream, g, s, round, kseed);
+    else if (g.pairs)
+        hipLaunchKernelGGL((k_retire<true, false>), grid, block, 0, L.stream, g, s, round, kseed);
+    else if (scatter)
+        hipLaunchKernelGGL((k_retire<false, true>), grid, block, 0, L.stream, g, s, round, kseed);
+    else
+        hipLaunchKernelGGL((k_retire<false, false>), grid, block, 0, L.stream, g, s, round, kseed);
     return hipGetLastError();
 }
 
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed) {
-    hipLaunchKernelGGL(k_max0_edge, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
+    if (g.pairs)
+        hipLaunchKernelGGL(k_max0_edge<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
+    else
+        hipLaunchKernelGGL(k_max0_edge<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
     hipLaunchKernelGGL(k_max0_vertex, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, seed);
     return hipGetLastError();
 }
@@ -978,8 +1000,12 @@ hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, in
 
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
                        uint32_t *bits, uint32_t kseed) {
-    hipLaunchKernelGGL(k_test, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round, clear_next,
-                       bits, kseed);
+    if (g.pairs)
+        hipLaunchKernelGGL(k_test<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round,
+                           clear_next, bits, kseed);
+    else
+        hipLaunchKernelGGL(k_test<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round,
+                           clear_next, bits, kseed);
     return hipGetLastError();
 }
 
