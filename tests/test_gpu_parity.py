@@ -167,6 +167,22 @@ def test_auto_vertex_form_hub_split(hgm, threshold):
     assert st["kernel_launches"]["vertex_max"] == 1 and st["kernel_launches"]["scatter"] == 0
 
 
+@pytest.mark.parametrize("threshold", [1, 64, 1000, 100_000])
+def test_auto_edge_form_hub_table(hgm, threshold):
+    """AUTO's edge-centric round 0 on skewed degrees reduces hub pins in a
+    per-workgroup LDS table of at most 512 hubs: threshold 1 overflows it
+    (the rest take the global path), 100,000 leaves it empty."""
+    import torch
+    g = synth.config_power_law(seed=23, n=40_000, m=100_000)
+    deg = g.degrees()
+    print(f"auto edge form threshold={threshold} hubs={(deg > threshold).sum()}", flush=True)
+    _check(hgm, g, 7, "auto", hub_threshold=threshold)
+    dg = hgm.DeviceHypergraph.from_host(g, "cuda:0")
+    _, st = hgm.match(dg, 7, hgm.make_opts("auto", hub_threshold=threshold), timing=True)
+    torch.cuda.synchronize()
+    assert st["kernel_launches"]["scatter"] == 1 and st["kernel_launches"]["vertex_max"] == 0
+
+
 def _hub_on_path(path_edges=201, hub_edges=20_000, seed=5):
     """A path with increasing weights (one match every two rounds from the top
     end) and a hub whose lighter 3-pin edges {hub, leaf, path vertex} die as
