@@ -20,6 +20,9 @@ constexpr int kMaxRoundsPerSync = 200;
 constexpr int kDefaultHubThreshold = 8192;
 constexpr int kBlocksPerCu = 8;
 constexpr int kEdgeGrid = 2048;  // workgroups of the edge kernels (fixed, device independent)
+// The test clears the whole next maximum buffer by streaming when a round has
+// at least n / kFullClearRatio live pins, else at each pin it visits.
+constexpr int kFullClearRatio = 8;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -380,6 +383,17 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             HGM_TRY(T.after(HGM_K_SCATTER, 0));
         }
     }
+    // Live pins of round r: the count itself once the host has read it, else
+    // the latest count shrunk by the latest per-round ratio.  It only picks
+    // the test's way of clearing, which is correct either way.
+    auto predicted_pins = [&](int r) -> double {
+        const int known = (int)live_p.size();  // live_p[i] = kappa_i for i < known
+        if (r < known) return (double)live_p[r];
+        const double last = (double)live_p.back();
+        const double prev = known >= 2 ? (double)live_p[known - 2] : last;
+        const double f = (prev > 0 && last < prev) ? last / prev : 1.0;
+        return last * std::pow(f, (double)(r - (known - 1)));
+    };
     int launched = 0;  // rounds whose test has been enqueued
     while (!finished) {
         int batch = next_batch(o, launched, live_p);
@@ -391,7 +405,10 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             const bool next_crew = crew_round(o, r + 1);
             // Clear the next round's max buffer when the next round scatters
             // (always in CRCW; at the switch from CREW to CRCW).
-            HGM_TRY(launch_test(L, g, s, r, next_crew ? 0 : 1, matched_bits, kseed(r)));
+            const int clear = next_crew ? kClearNone
+                              : predicted_pins(r) * kFullClearRatio >= (double)g.n ? kClearAll
+                                                                                    : kClearPins;
+            HGM_TRY(launch_test(L, g, s, r, clear, matched_bits, kseed(r)));
             HGM_TRY(T.after(HGM_K_TEST, r));
             HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1)));
             HGM_TRY(T.after(HGM_K_RETIRE, r));

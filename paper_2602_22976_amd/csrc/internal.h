@@ -145,7 +145,9 @@ hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, in
 // Round-0 maximum in the form chosen from the degree profile (AUTO): two
 // launches, of which the one not chosen returns at once.
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed);
-hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
+// How the test clears the next round's maximum buffer (see k_test).
+constexpr int kClearNone = 0, kClearAll = 1, kClearPins = 2;
+hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear,
                        uint32_t *bits, uint32_t kseed);
 
 }  // namespace hgm

@@ -732,21 +732,24 @@ __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32
 // a live edge is matched iff best[v] == key(e) at every pin v.  Matched edges
 // set their bitmap bit and mark their pins done (exclusive: a vertex has one
 // maximum edge).
-// With clear_next the next round's buffer best[(r+1) & 1] is zeroed: by one
-// streaming pass over all n entries when the round has many pins (kappa_r >=
-// n / 8: a full sequential clear is cheaper than as many scattered stores),
-// else at every pin this pass reads.  The next round's survivors are a subset
-// of this round's live edges, so the next scatter starts from zero at all of
-// its pins.  Workgroup 0 also clears the counters of round r+1.
-constexpr int kFullClearRatio = 8;
+// kClear says how the next round's buffer best[(r+1) & 1] is zeroed for the
+// next scatter (the next round's survivors are a subset of this round's
+// live edges, so zero at every pin this pass reads is enough):
+//   kClearNone  the next round is vertex-centric (it writes every entry)
+//   kClearAll   one streaming pass over all n entries, for rounds with many
+//               pins (a full sequential clear is cheaper than as many
+//               scattered stores); the test itself stops at the first pin
+//               where the edge is not the maximum
+//   kClearPins  a store at every pin of every live edge, all pins visited
+// The host picks the form from its latest count of live pins; any form is
+// correct.  Workgroup 0 also clears the counters of round r+1.
 constexpr int kTestEdges = 2;  // edges per lane and step of the early-exit test
 
 // kPairs: graph layout (instantiated separately; g.pairs equals it).
-template <bool kPairs>
-__global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, int clear_next,
-                                                 uint32_t *bits, uint32_t kseed) {
+template <bool kPairs, int kClear>
+__global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, uint32_t *bits,
+                                                 uint32_t kseed) {
     __shared__ ChunkLds L;
-    __shared__ int full_clear;
     const int b = blockIdx.x;
     const int cnt = region_count(s, g.m, round, b);
     const uint64_t *best = s.best[round & 1];
@@ -756,20 +759,11 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
         unsigned long long *z = (unsigned long long *)&s.stats[(round + 1) % s.ring];
         for (int i = threadIdx.x; i < (int)(sizeof(RoundStats) / 8); i += kBlock) z[i] = 0;
     }
-    if (clear_next) {
-        if (threadIdx.x < kWave) {
-            unsigned long long k = st_cur->kappa[threadIdx.x];
-#pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) k += __shfl_xor(k, o, kWave);
-            if (threadIdx.x == 0) full_clear = k * kFullClearRatio >= (unsigned long long)g.n;
-        }
-        __syncthreads();
-        if (full_clear) {
-            const int64_t stride = (int64_t)gridDim.x * kBlock;
-            for (int64_t v = (int64_t)b * kBlock + threadIdx.x; v < g.n; v += stride) next[v] = 0;
-        }
+    if constexpr (kClear == kClearAll) {
+        const int64_t stride = (int64_t)gridDim.x * kBlock;
+        for (int64_t v = (int64_t)b * kBlock + threadIdx.x; v < g.n; v += stride) next[v] = 0;
     }
-    const bool clear_pins = clear_next && !full_clear;
+    constexpr bool clear_pins = kClear == kClearPins;
     unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
     if constexpr (kPairs) {
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
@@ -777,7 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, in
             const int2 p = pair_pins(g, e);
             const uint64_t key = edge_key(g, s, kseed, e);
             const uint64_t b0 = best[p.x], b1 = best[p.y];
-            if (clear_pins) {
+            if constexpr (clear_pins) {
                 next[p.x] = 0;
                 next[p.y] = 0;
             }
@@ -998,14 +992,21 @@ hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, in
     return hipGetLastError();
 }
 
-hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear_next,
+hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear,
                        uint32_t *bits, uint32_t kseed) {
-    if (g.pairs)
-        hipLaunchKernelGGL(k_test<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round,
-                           clear_next, bits, kseed);
-    else
-        hipLaunchKernelGGL(k_test<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, round,
-                           clear_next, bits, kseed);
+    const dim3 grid(s.grid), block(kBlock);
+#define HGM_TEST(P, C) \
+    hipLaunchKernelGGL((k_test<P, C>), grid, block, 0, L.stream, g, s, round, bits, kseed)
+    if (g.pairs) {
+        if (clear == kClearAll) HGM_TEST(true, kClearAll);
+        else if (clear == kClearPins) HGM_TEST(true, kClearPins);
+        else HGM_TEST(true, kClearNone);
+    } else {
+        if (clear == kClearAll) HGM_TEST(false, kClearAll);
+        else if (clear == kClearPins) HGM_TEST(false, kClearPins);
+        else HGM_TEST(false, kClearNone);
+    }
+#undef HGM_TEST
     return hipGetLastError();
 }
 
