@@ -36,9 +36,13 @@ constexpr int kWaves = kBlock / kWave;
 // Key of edge e in a round whose priority seed is kseed.  A batch stores its
 // keys (each instance has its own seed and local ids); one instance rebuilds
 // them from the 4-byte weight, half the bytes of a stored key.
+// kB (here and below): the kernels run on a batch (stored keys, per-edge
+// vertex bases, bitmap offsets) rather than one instance; each kernel is
+// instantiated for both and the host launches the one that applies.
+template <bool kB>
 __device__ __forceinline__ uint64_t edge_key(const Graph &g, const State &s, uint32_t kseed,
                                              int e) {
-    if (s.key) return s.key[e];
+    if constexpr (kB) return s.key[e];
     return ((uint64_t)g.w[e] << 32) | priority_hash(kseed, (uint32_t)e);
 }
 
@@ -125,6 +129,7 @@ constexpr int kUnroll = 4;
 
 // The kUnroll incidences t0, t0 + kBlock, ... of the current chunk: item
 // index j (-1 past the end) and pin.
+template <bool kB>
 __device__ __forceinline__ void chunk_pins(const ChunkLds &L, const int32_t *e_pins, int total,
                                            int t0, int (&j)[kUnroll], int (&pin)[kUnroll]) {
 #pragma unroll
@@ -134,7 +139,9 @@ __device__ __forceinline__ void chunk_pins(const ChunkLds &L, const int32_t *e_p
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-        pin[u] = j[u] >= 0 ? e_pins[L.base[j[u]] + (t0 + u * kBlock - L.start[j[u]])] + L.vb[j[u]] : 0;
+        pin[u] = j[u] >= 0 ? e_pins[L.base[j[u]] + (t0 + u * kBlock - L.start[j[u]])] +
+                                 (kB ? L.vb[j[u]] : 0)
+                           : 0;
 }
 
 // Raises best[pin] to the chunk items' keys over a flattened loop.  The
@@ -143,11 +150,12 @@ __device__ __forceinline__ void chunk_pins(const ChunkLds &L, const int32_t *e_p
 // One incidence per lane and step: issuing more reads before the atomics
 // makes more of them see stale values and turns filtered reads into atomics,
 // which cost far more on this hardware than the latency saved.
+template <bool kB>
 __device__ __forceinline__ void scatter_chunk(const ChunkLds &L, const int32_t *e_pins, int total,
                                               uint64_t *best) {
     for (int t = threadIdx.x; t < total; t += kBlock) {
         const int j = find_item(L.start, t);
-        const int pin = e_pins[L.base[j] + (t - L.start[j])] + L.vb[j];
+        const int pin = e_pins[L.base[j] + (t - L.start[j])] + (kB ? L.vb[j] : 0);
         const uint64_t k = L.key[j];
         if (load_lower_bound(&best[pin]) < k) atomic_max_u64(&best[pin], k);
     }
@@ -205,11 +213,12 @@ __device__ void hub_table_build(HubTable &H, const State &s) {
 }
 
 // scatter_chunk with hub pins reduced in the table.
+template <bool kB>
 __device__ __forceinline__ void scatter_chunk_hubs(const ChunkLds &L, const int32_t *e_pins,
                                                    int total, uint64_t *best, HubTable &H) {
     for (int t = threadIdx.x; t < total; t += kBlock) {
         const int j = find_item(L.start, t);
-        const int pin = e_pins[L.base[j] + (t - L.start[j])] + L.vb[j];
+        const int pin = e_pins[L.base[j] + (t - L.start[j])] + (kB ? L.vb[j] : 0);
         const uint64_t k = L.key[j];
         const int h = hub_find(H, pin);
         if (h >= 0) {
@@ -263,7 +272,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     const int64_t top = span > words ? span : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
-        if (i < g.m && (flags & kInitLiveKey)) s.live_key[i] = edge_key(g, s, seed, (int)i);
+        if (i < g.m && (flags & kInitLiveKey))
+            s.live_key[i] = s.key ? edge_key<true>(g, s, seed, (int)i) : edge_key<false>(g, s, seed, (int)i);
         if (i < g.n) {
             s.best[0][i] = 0;
             s.done[i] = 0;
@@ -355,7 +365,7 @@ __device__ __forceinline__ int region_item(const State &s, int round, int b, int
 // key; best only grows during the pass, so a stale read is merely cautious.
 // With a hub table H (AUTO's round 0), hub pins are reduced in LDS and
 // pushed once per workgroup at the end.
-template <bool kPairs>
+template <bool kPairs, bool kB>
 __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, ChunkLds &L, int b,
                                                 uint32_t kseed, HubTable *H = nullptr) {
     uint64_t *best = s.best[0];
@@ -363,7 +373,7 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
     if constexpr (kPairs) {
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
             const int e = region_item(s, 0, b, i);
-            scatter_pair(best, pair_pins(g, e), edge_key(g, s, kseed, e));
+            scatter_pair(best, pair_pins(g, e), edge_key<kB>(g, s, kseed, e));
         }
         return;
     }
@@ -376,8 +386,8 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
             const int e = region_item(s, 0, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = edge_key(g, s, kseed, e);
-            if (g.vbase) vb = g.vbase[e];
+            key = edge_key<kB>(g, s, kseed, e);
+            if constexpr (kB) vb = g.vbase[e];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
@@ -387,9 +397,9 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
         L.vb[threadIdx.x] = vb;
         __syncthreads();
         if (H)
-            scatter_chunk_hubs(L, g.e_pins, total, best, *H);
+            scatter_chunk_hubs<kB>(L, g.e_pins, total, best, *H);
         else
-            scatter_chunk(L, g.e_pins, total, best);
+            scatter_chunk<kB>(L, g.e_pins, total, best);
         __syncthreads();
     }
     if (H) {
@@ -401,10 +411,10 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
     }
 }
 
-template <bool kPairs>
+template <bool kPairs, bool kB>
 __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t kseed) {
     __shared__ ChunkLds L;
-    scatter0_region<kPairs>(g, s, L, blockIdx.x, kseed);
+    scatter0_region<kPairs, kB>(g, s, L, blockIdx.x, kseed);
 }
 
 // ---------------------------------------------------------------------------
@@ -422,7 +432,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 // kPairs: graph layout; kScatter: the CRCW form (else CREW).  Each
 // combination is its own kernel: a kernel holding every path runs the hot
 // one slower.
-template <bool kPairs, bool kScatter>
+template <bool kPairs, bool kScatter, bool kB>
 __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed) {
     constexpr bool scatter = kScatter;
     __shared__ ChunkLds L;
@@ -459,7 +469,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             const int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
             if (alive) {
                 out_list[out_pos + pos] = e;
-                if (scatter) scatter_pair(best, p, edge_key(g, s, kseed, e));
+                if (scatter) scatter_pair(best, p, edge_key<kB>(g, s, kseed, e));
             }
             out_pos += n_alive;
         }
@@ -474,8 +484,8 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             e = region_item(s, round - 1, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = edge_key(g, s, kseed, e);
-            if (g.vbase) vb = g.vbase[e];
+            key = edge_key<kB>(g, s, kseed, e);
+            if constexpr (kB) vb = g.vbase[e];
         }
         // The first kUnroll pins one lane per edge: most retired edges are
         // found there, and most edges have no more pins.  The pins beyond
@@ -505,7 +515,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
                 __syncthreads();
                 for (int t0 = threadIdx.x; t0 < total_r; t0 += kUnroll * kBlock) {
                     int jj[kUnroll], pin[kUnroll];
-                    chunk_pins(L, g.e_pins, total_r, t0, jj, pin);
+                    chunk_pins<kB>(L, g.e_pins, total_r, t0, jj, pin);
                     uint8_t dv[kUnroll];
 #pragma unroll
                     for (int u = 0; u < kUnroll; ++u) dv[u] = jj[u] >= 0 ? s.done[pin[u]] : 0;
@@ -533,7 +543,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         if (scatter) {
             L.start[threadIdx.x] = st2;
             __syncthreads();
-            scatter_chunk(L, g.e_pins, total2, best);
+            scatter_chunk<kB>(L, g.e_pins, total2, best);
         }
         __syncthreads();
     }
@@ -568,13 +578,14 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // whole list.  Round 1 reads the caller's lists.  Non-hub positions come from
 // an LDS counter per vertex; a hub's from one global atomic per wave on its
 // vlen entry (cleared by the retire pass).
+template <bool kB>
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
                                                uint32_t seed, int e) {
-    return round == 0 ? edge_key(g, s, seed, e) : s.live_key[e];
+    return round == 0 ? edge_key<kB>(g, s, seed, e) : s.live_key[e];
 }
 
 // kCompact: rounds >= 1 (list compaction); round 0 instantiates without it.
-template <bool kCompact>
+template <bool kCompact, bool kB>
 __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, ChunkLds &L,
                                                 int round, uint32_t seed) {
     uint64_t *best = s.best[round & 1];
@@ -599,7 +610,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         const int p0 = pc.y * kHubPiece;
         if (p0 >= len) continue;
         const int p1 = min(len, p0 + kHubPiece);
-        const int eb = (caller_lists && g.ebase) ? g.ebase[v] : 0;
+        const int eb = (kB && caller_lists) ? g.ebase[v] : 0;
         uint64_t mx = 0;
         for (int i0 = p0; i0 < p1; i0 += kBlock) {  // uniform trip count (ballot below)
             const int i = i0 + threadIdx.x;
@@ -607,7 +618,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             uint64_t k = 0;
             if (i < p1) {
                 e = src[vo + i] + eb;
-                k = vertex_key(g, s, round, seed, e);
+                k = vertex_key<kB>(g, s, round, seed, e);
             }
             mx = k > mx ? k : mx;
             if constexpr (compact) {
@@ -636,7 +647,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             base = g.v_off[v];
             own = g.v_off[v + 1] - base <= hub_threshold;
             if (own) len = src_len ? src_len[v] : g.v_off[v + 1] - base;
-            if (caller_lists && g.ebase) eb = g.ebase[v];
+            if (kB && caller_lists) eb = g.ebase[v];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
@@ -652,8 +663,8 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             uint64_t k = 0;
             if (t < total) {
                 j = find_item(L.start, t);
-                const int e = src[L.base[j] + (t - L.start[j])] + L.vb[j];
-                k = vertex_key(g, s, round, seed, e);
+                const int e = src[L.base[j] + (t - L.start[j])] + (kB ? L.vb[j] : 0);
+                k = vertex_key<kB>(g, s, round, seed, e);
                 if constexpr (compact) {
                     if (k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
                 }
@@ -678,12 +689,13 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
     }
 }
 
+template <bool kB>
 __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, uint32_t seed) {
     __shared__ ChunkLds L;
     if (round == 0)
-        vertex_max_body<false>(g, s, L, round, seed);
+        vertex_max_body<false, kB>(g, s, L, round, seed);
     else
-        vertex_max_body<true>(g, s, L, round, seed);
+        vertex_max_body<true, kB>(g, s, L, round, seed);
 }
 
 // Round-0 maximum when the library chooses the form (AUTO).  The edge-centric
@@ -710,7 +722,7 @@ __device__ __forceinline__ bool max0_edge_form(const Graph &g, const State &s) {
     return edge_form != 0;
 }
 
-template <bool kPairs>
+template <bool kPairs, bool kB>
 __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t seed) {
     __shared__ ChunkLds L;
     __shared__ HubTable H;
@@ -718,13 +730,14 @@ __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
     if (!edge_form) return;
     hub_table_build(H, s);
-    scatter0_region<kPairs>(g, s, L, blockIdx.x, seed, &H);
+    scatter0_region<kPairs, kB>(g, s, L, blockIdx.x, seed, &H);
 }
 
+template <bool kB>
 __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32_t seed) {
     __shared__ ChunkLds L;
     if (max0_edge_form(g, s)) return;
-    vertex_max_body<false>(g, s, L, 0, seed);
+    vertex_max_body<false, kB>(g, s, L, 0, seed);
 }
 
 // ---------------------------------------------------------------------------
@@ -746,7 +759,7 @@ __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32
 constexpr int kTestEdges = 2;  // edges per lane and step of the early-exit test
 
 // kPairs: graph layout (instantiated separately; g.pairs equals it).
-template <bool kPairs, int kClear>
+template <bool kPairs, int kClear, bool kB>
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, uint32_t *bits,
                                                  uint32_t kseed) {
     __shared__ ChunkLds L;
@@ -769,14 +782,14 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
             const int e = region_item(s, round, b, i);
             const int2 p = pair_pins(g, e);
-            const uint64_t key = edge_key(g, s, kseed, e);
+            const uint64_t key = edge_key<kB>(g, s, kseed, e);
             const uint64_t b0 = best[p.x], b1 = best[p.y];
             if constexpr (clear_pins) {
                 next[p.x] = 0;
                 next[p.y] = 0;
             }
             if (b0 == key && b1 == key) {
-                const int bit = g.bitoff ? e + g.bitoff[e] : e;
+                const int bit = kB ? e + g.bitoff[e] : e;
                 atomicOr(&bits[bit >> 5], 1u << (bit & 31));
                 nm += 1;
                 wm += key >> 32;
@@ -789,7 +802,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
     // A matched edge sets its bit and marks its pins (no other live edge
     // shares a pin with it in this round).
     auto record = [&](int e, int base, int len, int vb, uint64_t key) {
-        const int bit = g.bitoff ? e + g.bitoff[e] : e;
+        const int bit = kB ? e + g.bitoff[e] : e;
         atomicOr(&bits[bit >> 5], 1u << (bit & 31));
         nm += 1;
         wm += key >> 32;
@@ -817,8 +830,8 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
                 if (e[u] >= 0) {
                     base[u] = g.e_off[e[u]];
                     len[u] = g.e_off[e[u] + 1] - base[u];
-                    key[u] = edge_key(g, s, kseed, e[u]);
-                    if (g.vbase) vb[u] = g.vbase[e[u]];
+                    key[u] = edge_key<kB>(g, s, kseed, e[u]);
+                    if constexpr (kB) vb[u] = g.vbase[e[u]];
                 }
             }
 #pragma unroll
@@ -853,8 +866,8 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
             e = region_item(s, round, b, i);
             base = g.e_off[e];
             len = g.e_off[e + 1] - base;
-            key = edge_key(g, s, kseed, e);
-            if (g.vbase) vb = g.vbase[e];
+            key = edge_key<kB>(g, s, kseed, e);
+            if constexpr (kB) vb = g.vbase[e];
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
@@ -866,7 +879,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         __syncthreads();
         for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
             int j[kUnroll], pin[kUnroll];
-            chunk_pins(L, g.e_pins, total, t0, j, pin);
+            chunk_pins<kB>(L, g.e_pins, total, t0, j, pin);
             uint64_t bv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) bv[u] = j[u] >= 0 ? best[pin[u]] : 0;
@@ -955,57 +968,79 @@ hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int 
     return hipGetLastError();
 }
 
+// Launch helpers: the instantiation follows the layout (graph pairs or
+// offsets) and whether the graph is a batch (g.vbase set); batches of graphs
+// in the pair layout are rejected by the interface.
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed) {
+    const dim3 grid(s.grid), block(kBlock);
     if (g.pairs)
-        hipLaunchKernelGGL(k_scatter0<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
+        hipLaunchKernelGGL((k_scatter0<true, false>), grid, block, 0, L.stream, g, s, kseed);
+    else if (g.vbase)
+        hipLaunchKernelGGL((k_scatter0<false, true>), grid, block, 0, L.stream, g, s, kseed);
     else
-        hipLaunchKernelGGL(k_scatter0<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, kseed);
+        hipLaunchKernelGGL((k_scatter0<false, false>), grid, block, 0, L.stream, g, s, kseed);
     return hipGetLastError();
 }
 
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
                          uint32_t kseed) {
     const dim3 grid(s.grid), block(kBlock);
-    if (g.pairs && scatter)
-        hipLaunchKernelGGL((k_retire<true, true>), grid, block, 0, L.stream, g, s, round, kseed);
-    else if (g.pairs)
-        hipLaunchKernelGGL((k_retire<true, false>), grid, block, 0, L.stream, g, s, round, kseed);
-    else if (scatter)
-        hipLaunchKernelGGL((k_retire<false, true>), grid, block, 0, L.stream, g, s, round, kseed);
-    else
-        hipLaunchKernelGGL((k_retire<false, false>), grid, block, 0, L.stream, g, s, round, kseed);
+#define HGM_RETIRE(P, S, B) \
+    hipLaunchKernelGGL((k_retire<P, S, B>), grid, block, 0, L.stream, g, s, round, kseed)
+    if (g.pairs) {
+        if (scatter) HGM_RETIRE(true, true, false);
+        else HGM_RETIRE(true, false, false);
+    } else if (g.vbase) {
+        if (scatter) HGM_RETIRE(false, true, true);
+        else HGM_RETIRE(false, false, true);
+    } else {
+        if (scatter) HGM_RETIRE(false, true, false);
+        else HGM_RETIRE(false, false, false);
+    }
+#undef HGM_RETIRE
     return hipGetLastError();
 }
 
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed) {
+    const dim3 eg(s.grid), vg(L.grid), block(kBlock);
     if (g.pairs)
-        hipLaunchKernelGGL(k_max0_edge<true>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
+        hipLaunchKernelGGL((k_max0_edge<true, false>), eg, block, 0, L.stream, g, s, seed);
+    else if (g.vbase)
+        hipLaunchKernelGGL((k_max0_edge<false, true>), eg, block, 0, L.stream, g, s, seed);
     else
-        hipLaunchKernelGGL(k_max0_edge<false>, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, seed);
-    hipLaunchKernelGGL(k_max0_vertex, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, seed);
+        hipLaunchKernelGGL((k_max0_edge<false, false>), eg, block, 0, L.stream, g, s, seed);
+    if (g.vbase)
+        hipLaunchKernelGGL(k_max0_vertex<true>, vg, block, 0, L.stream, g, s, seed);
+    else
+        hipLaunchKernelGGL(k_max0_vertex<false>, vg, block, 0, L.stream, g, s, seed);
     return hipGetLastError();
 }
 
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
                              uint32_t seed) {
-    hipLaunchKernelGGL(k_vertex_max, dim3(L.grid), dim3(kBlock), 0, L.stream, g, s, round, seed);
+    const dim3 grid(L.grid), block(kBlock);
+    if (g.vbase)
+        hipLaunchKernelGGL(k_vertex_max<true>, grid, block, 0, L.stream, g, s, round, seed);
+    else
+        hipLaunchKernelGGL(k_vertex_max<false>, grid, block, 0, L.stream, g, s, round, seed);
     return hipGetLastError();
 }
 
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear,
                        uint32_t *bits, uint32_t kseed) {
     const dim3 grid(s.grid), block(kBlock);
-#define HGM_TEST(P, C) \
-    hipLaunchKernelGGL((k_test<P, C>), grid, block, 0, L.stream, g, s, round, bits, kseed)
-    if (g.pairs) {
-        if (clear == kClearAll) HGM_TEST(true, kClearAll);
-        else if (clear == kClearPins) HGM_TEST(true, kClearPins);
-        else HGM_TEST(true, kClearNone);
-    } else {
-        if (clear == kClearAll) HGM_TEST(false, kClearAll);
-        else if (clear == kClearPins) HGM_TEST(false, kClearPins);
-        else HGM_TEST(false, kClearNone);
-    }
+#define HGM_TEST(P, C, B) \
+    hipLaunchKernelGGL((k_test<P, C, B>), grid, block, 0, L.stream, g, s, round, bits, kseed)
+#define HGM_TEST_CLEAR(P, B)                                        \
+    do {                                                            \
+        if (clear == kClearAll) HGM_TEST(P, kClearAll, B);          \
+        else if (clear == kClearPins) HGM_TEST(P, kClearPins, B);   \
+        else HGM_TEST(P, kClearNone, B);                            \
+    } while (0)
+    if (g.pairs) HGM_TEST_CLEAR(true, false);
+    else if (g.vbase) HGM_TEST_CLEAR(false, true);
+    else HGM_TEST_CLEAR(false, false);
+#undef HGM_TEST_CLEAR
 #undef HGM_TEST
     return hipGetLastError();
 }
