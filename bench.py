@@ -9,6 +9,9 @@ Printed (one JSON line):
   value        live pin incidences processed per second, sum over rounds of
                kappa_r divided by the step time (the per-round incidence
                throughput of the method, all overheads included)
+  per_round    |L_r|, kappa_r, device time and kappa_r / t_r of each round;
+               work_inflation = sum kappa_r / kappa; kernel_incidences_per_s
+               = sum kappa_r over the summed kernel time
   roofline     the dominant kernel's algorithmic bytes / its HIP-event time,
                against the 8 TB/s HBM peak; `traffic` from the committed
                rocprofv3 PMC summary when it matches the kernel source
@@ -272,6 +275,17 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2):
             "arena_peak_gb": info["arena_peak"] / (1 << 30)}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(g, seed, budget_s):
     import numpy as np
     import oracle
@@ -289,6 +303,7 @@ def cpu_baseline(g, seed, budget_s):
     tg = time.perf_counter() - tg0
     sum_k = int(np.sum(stats["live_pins"]))
     return {"value": sum_k / t, "unit": "pin-incidences/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": (f"oracle round simulator (one thread) on the full workload, {runs} run(s) "
                        f"of {t:.3f} s each, {stats['rounds']} rounds, sum kappa_r = {sum_k}; "
                        f"oracle greedy on the same input: {tg:.3f} s")}
@@ -309,7 +324,7 @@ def cpu_multicore(g, seed, budget_s):
             break
     t = (time.perf_counter() - t0) / runs
     return {"value": sum_k / t, "unit": "pin-incidences/s", "cores": threads,
-            "kind": "openmp local max",
+            "kind": "openmp local max", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": (f"multicore CPU local max ({threads} threads) on the full workload, "
                        f"{runs} run(s) of {t:.3f} s each, {rounds} rounds, sum kappa_r = {sum_k}")}
 
@@ -322,6 +337,8 @@ def main():
     ap.add_argument("--workload", default="power-law", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto", choices=["auto", "crcw", "crew"])
     ap.add_argument("--rounds-per-sync", type=int, default=0)
+    ap.add_argument("--hub-threshold", type=int, default=0,
+                    help="degree above which a vertex is split into pieces (0 = library default)")
     ap.add_argument("--cpu-baseline", type=float, default=10.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
     ap.add_argument("--cpu-multicore", type=float, default=3.0,
@@ -374,7 +391,8 @@ def main():
         print("bench.py: graph workloads run the edge-centric rounds (auto or crcw)",
               file=sys.stderr)
         sys.exit(2)
-    opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync, pairs=pairs)
+    opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync, pairs=pairs,
+                         hub_threshold=args.hub_threshold)
     ws = hgm.alloc_workspace(dg, opts)
     bits = torch.empty(max((g.m + 31) // 32, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
@@ -401,8 +419,14 @@ def main():
     launches = {}
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = []       # each of these steps ends in a synchronisation (the stats copy)
+    round_ms = None    # per-round device time, summed over the steps
     for _ in range(args.steps):
+        ts = time.perf_counter()
         sti = step(timing=True)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
+        rm = np.asarray(sti["round_ms"], dtype=np.float64)
+        round_ms = rm if round_ms is None else round_ms + rm
         for k, v in sti["kernel_ms"].items():
             tot_ms[k] = tot_ms.get(k, 0.0) + v
             launches[k] = launches.get(k, 0) + sti["kernel_launches"][k]
@@ -434,7 +458,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "kappa": g.kappa,
-                   "variant": args.variant, "rounds": st["rounds"],
+                   "variant": args.variant, "hub_threshold": args.hub_threshold or None,
+                   "rounds": st["rounds"],
                    "sum_kappa_r": sum_k, "matched": st["matched"]},
         "input_incidences_per_s": g.kappa / t_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -445,9 +470,15 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in tot_ms.items()},
         "kernel_launches_per_step": {k: v / args.steps for k, v in launches.items()},
         "ms_per_step_with_events": t_step_events * 1e3,
+        "ms_per_step_median": float(np.median(step_ms)),
+        "work_inflation": sum_k / max(g.kappa, 1),
+        "kernel_incidences_per_s": sum_k / (sum(tot_ms.values()) / args.steps * 1e-3),
         "per_round": {"live_edges": [int(x) for x in st["live_edges"]],
                       "live_pins": [int(x) for x in st["live_pins"]],
-                      "round_ms": [round(float(x), 4) for x in sti["round_ms"]]},
+                      "round_ms": [round(float(x), 4) for x in round_ms / args.steps],
+                      "incidences_per_s": [float(k / (t * 1e-3)) if t > 0 else None
+                                           for k, t in zip(st["live_pins"],
+                                                           round_ms / args.steps)]},
         "batched": None,
         "served": None,
         "cpu_baseline": None,
