@@ -203,7 +203,8 @@ def batched_leg(count, steps):
             "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same}
 
 
-def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2):
+def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2,
+               edge_side_only=True):
     """Open-loop Poisson arrivals at `rate` req/s for `duration` s into the
     request server.  Requests are drawn (seeded) from a pool of pre-generated
     hypergraphs in pinned host memory (kappa log-uniform in [1e3, 1e7],
@@ -235,7 +236,8 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2):
     gen_s = time.perf_counter() - t0
     arrivals = synth.gen.poisson_arrivals(2005, rate, duration)
     pick = np.random.Generator(np.random.PCG64(3005)).integers(0, len(views), size=arrivals.size)
-    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"))
+    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"),
+                     edge_side_only=edge_side_only)
     sched = {}
     done = []
     start = time.monotonic() + 0.05
@@ -267,6 +269,7 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2):
     return {"rate": rate, "duration_s": duration, "requests": int(arrivals.size),
             "completed": len(ok), "failed": len(done) - len(ok), "pool": pool_count,
             "pool_generated_s": round(gen_s, 1), "workers": workers, "budget_gb": budget_gb,
+            "edge_side_only": edge_side_only,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_ms": float(lat.mean() * 1e3),
             "hypergraphs_per_s": len(ok) / (end - start),
@@ -350,7 +353,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-vertex-side", type=int, default=0,
+                    help="1: requests also upload the vertex side (default: edge side only)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
     args = ap.parse_args()
@@ -488,7 +493,8 @@ def main():
         result["batched"] = batched_leg(args.batch_count, max(1, min(args.steps, 5)))
     if args.serve_seconds > 0:
         result["served"] = served_leg(args.serve_rate, args.serve_seconds, args.serve_pool,
-                                      args.serve_budget_gb, args.serve_workers)
+                                      args.serve_budget_gb, args.serve_workers,
+                                      edge_side_only=not args.serve_vertex_side)
     if args.cpu_baseline > 0:
         result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
     if args.cpu_multicore > 0:

@@ -68,7 +68,8 @@ class HgmResult(ctypes.Structure):
 
 
 class HgmServerOpts(ctypes.Structure):
-    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("match", HgmOpts)]
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("match", HgmOpts),
+                ("edge_side_only", ctypes.c_int32)]
 
 
 class HgmServerState(ctypes.Structure):
@@ -374,11 +375,13 @@ class Server:
     poll() returns finished results as dicts with the output bitmap."""
 
     def __init__(self, arena_bytes, workers=2, max_batch=0, opts: HgmOpts | None = None,
-                 device="cuda:0"):
+                 device="cuda:0", edge_side_only=False):
         torch = _torch()
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         so = HgmServerOpts()
         so.workers, so.max_batch = workers, max_batch
+        so.edge_side_only = 1 if edge_side_only else 0
+        self.edge_side_only = bool(edge_side_only)
         if opts is not None:
             so.match = opts
         h = ctypes.c_void_p()
@@ -394,16 +397,17 @@ class Server:
         import numpy as np
         rid = self.next_id if req_id is None else int(req_id)
         self.next_id = max(self.next_id, rid) + 1
+        vside = not self.edge_side_only   # else the vertex side is not sent
         arrs = [np.ascontiguousarray(g.e_off, dtype=np.int32),
                 np.ascontiguousarray(g.e_pins, dtype=np.int32),
-                np.ascontiguousarray(g.v_off, dtype=np.int32),
-                np.ascontiguousarray(g.v_edges, dtype=np.int32),
+                np.ascontiguousarray(g.v_off, dtype=np.int32) if vside else None,
+                np.ascontiguousarray(g.v_edges, dtype=np.int32) if vside else None,
                 np.ascontiguousarray(g.w, dtype=np.uint32)]
         out = np.zeros(max((g.m + 31) // 32, 1), dtype=np.uint32)
         q = HgmRequest()
         q.id, q.n, q.m, q.kappa = rid, g.n, g.m, int(arrs[1].size)
-        q.e_off, q.e_pins, q.v_off, q.v_edges, q.w = [a.ctypes.data_as(ctypes.c_void_p)
-                                                      for a in arrs]
+        q.e_off, q.e_pins, q.v_off, q.v_edges, q.w = [
+            a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs]
         q.seed = seed & 0xFFFFFFFF
         q.bits_out = out.ctypes.data_as(ctypes.c_void_p)
         self.live[rid] = (arrs, out, g.m)

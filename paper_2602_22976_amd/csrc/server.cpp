@@ -119,7 +119,8 @@ namespace {
 // Sizes of a wave holding the given totals; the workspace is sized by
 // hgm_batch_workspace_size on a descriptor with those totals.
 WaveLayout wave_layout(int count, int64_t n, int64_t m, int64_t kappa, int64_t words,
-                       const hgm_opts *mopts) {
+                       const hgm_server_opts &o) {
+    const bool vside = !o.edge_side_only;
     WaveLayout L;
     size_t at = 0;
     auto take = [&](size_t bytes) {
@@ -134,8 +135,8 @@ WaveLayout wave_layout(int count, int64_t n, int64_t m, int64_t kappa, int64_t w
     L.seeds = take(4 * (size_t)count);
     L.e_off = take(4 * (size_t)(m + count));
     L.e_pins = take(4 * (size_t)kappa);
-    L.v_off = take(4 * (size_t)(n + count));
-    L.v_edges = take(4 * (size_t)kappa);
+    L.v_off = take(vside ? 4 * (size_t)(n + count) : 0);
+    L.v_edges = take(vside ? 4 * (size_t)kappa : 0);
     L.w = take(4 * (size_t)m);
     L.bits = take(4 * (size_t)words);
     hgm_batch d;
@@ -147,9 +148,10 @@ WaveLayout wave_layout(int count, int64_t n, int64_t m, int64_t kappa, int64_t w
     d.words_total = words;
     // Non-NULL placeholders: only sizes and the presence of the vertex side matter.
     d.v_base = d.e_base = d.pin_base = d.word_base = (const int64_t *)(uintptr_t)256;
-    d.e_off = d.e_pins = d.v_off = d.v_edges = (const int32_t *)(uintptr_t)256;
+    d.e_off = d.e_pins = (const int32_t *)(uintptr_t)256;
+    if (vside) d.v_off = d.v_edges = (const int32_t *)(uintptr_t)256;
     d.w = d.seeds = (const uint32_t *)(uintptr_t)256;
-    L.ws_bytes = hgm_batch_workspace_size(&d, mopts);
+    L.ws_bytes = hgm_batch_workspace_size(&d, &o.match);
     L.ws = take(L.ws_bytes);
     L.total = at;
     return L;
@@ -179,6 +181,7 @@ int run_wave(hgm_server *S, hipStream_t stream, const std::vector<Pending> &wave
              const WaveLayout &L, int64_t n, int64_t m, int64_t kappa, int64_t words) {
     char *blk = S->arena_base + off;
     const int count = (int)wave.size();
+    const bool vside = !S->opts.edge_side_only;
     std::vector<int64_t> vb(count + 1), eb(count + 1), pb(count + 1), wb(count + 1);
     std::vector<uint32_t> seeds(count);
     vb[0] = eb[0] = pb[0] = wb[0] = 0;
@@ -219,11 +222,13 @@ int run_wave(hgm_server *S, hipStream_t stream, const std::vector<Pending> &wave
         if (q.kappa > 0) {
             SRV_TRY(hipMemcpyAsync(blk + L.e_pins + 4 * pb[i], q.e_pins, 4 * (size_t)q.kappa,
                                    hipMemcpyHostToDevice, stream));
-            SRV_TRY(hipMemcpyAsync(blk + L.v_edges + 4 * pb[i], q.v_edges, 4 * (size_t)q.kappa,
-                                   hipMemcpyHostToDevice, stream));
+            if (vside)
+                SRV_TRY(hipMemcpyAsync(blk + L.v_edges + 4 * pb[i], q.v_edges,
+                                       4 * (size_t)q.kappa, hipMemcpyHostToDevice, stream));
         }
-        SRV_TRY(hipMemcpyAsync(blk + L.v_off + 4 * (vb[i] + i), q.v_off, 4 * ((size_t)q.n + 1),
-                               hipMemcpyHostToDevice, stream));
+        if (vside)
+            SRV_TRY(hipMemcpyAsync(blk + L.v_off + 4 * (vb[i] + i), q.v_off, 4 * ((size_t)q.n + 1),
+                                   hipMemcpyHostToDevice, stream));
     }
     hgm_batch d;
     memset(&d, 0, sizeof(d));
@@ -239,8 +244,8 @@ int run_wave(hgm_server *S, hipStream_t stream, const std::vector<Pending> &wave
     d.seeds = (const uint32_t *)(blk + L.seeds);
     d.e_off = (const int32_t *)(blk + L.e_off);
     d.e_pins = (const int32_t *)(blk + L.e_pins);
-    d.v_off = (const int32_t *)(blk + L.v_off);
-    d.v_edges = (const int32_t *)(blk + L.v_edges);
+    d.v_off = vside ? (const int32_t *)(blk + L.v_off) : nullptr;
+    d.v_edges = vside ? (const int32_t *)(blk + L.v_edges) : nullptr;
     d.w = (const uint32_t *)(blk + L.w);
     int rc = hgm_match_batch(&d, (uint32_t *)(blk + L.bits), blk + L.ws, L.ws_bytes,
                              &S->opts.match, stream, nullptr);
@@ -287,8 +292,7 @@ void worker_main(hgm_server *S) {
                     const hgm_request &q = S->queue[i].req;
                     const WaveLayout T = wave_layout((int)wave.size() + 1, n + q.n, m + q.m,
                                                      kappa + q.kappa,
-                                                     words + (int64_t)words_of(q.m),
-                                                     &S->opts.match);
+                                                     words + (int64_t)words_of(q.m), S->opts);
                     size_t probe;
                     if (!S->arena.alloc(T.total, &probe)) {
                         if (wave.empty() && T.total > S->arena.size()) fits_alone = false;
@@ -312,7 +316,7 @@ void worker_main(hgm_server *S) {
                     continue;
                 }
                 if (!wave.empty()) {
-                    L = wave_layout((int)wave.size(), n, m, kappa, words, &S->opts.match);
+                    L = wave_layout((int)wave.size(), n, m, kappa, words, S->opts);
                     (void)best;
                     if (S->arena.alloc(L.total, &off)) break;
                 }
@@ -354,6 +358,9 @@ int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *op
     if (opts) o = *opts;
     if (o.workers < 0 || o.max_batch < 0 || o.workers > 64) return HGM_E_ARG;
     if (o.match.validate) return HGM_E_ARG;
+    if (o.edge_side_only != 0 && o.edge_side_only != 1) return HGM_E_ARG;
+    // Without the vertex side only the edge-centric rounds can run.
+    if (o.edge_side_only && o.match.variant == HGM_VARIANT_CREW) return HGM_E_ARG;
     if (o.workers == 0) o.workers = 2;
     if (o.max_batch == 0) o.max_batch = 1024;
     int dev = 0;
@@ -370,9 +377,9 @@ int hgm_server_submit(hgm_server *S, const hgm_request *req) {
     if (!S || !req) return HGM_E_ARG;
     const hgm_request &q = *req;
     if (q.n < 0 || q.m < 0 || q.kappa < 0 || q.kappa >= ((int64_t)1 << 31)) return HGM_E_ARG;
-    if (!q.v_off || (q.m > 0 && (!q.e_off || !q.w || !q.bits_out)) ||
-        (q.kappa > 0 && (!q.e_pins || !q.v_edges)))
+    if ((q.m > 0 && (!q.e_off || !q.w || !q.bits_out)) || (q.kappa > 0 && !q.e_pins))
         return HGM_E_ARG;
+    if (!S->opts.edge_side_only && (!q.v_off || (q.kappa > 0 && !q.v_edges))) return HGM_E_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) return HGM_E_ARG;
     S->queue.push_back(Pending{q, now_s()});

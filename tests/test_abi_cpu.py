@@ -170,6 +170,12 @@ def test_server_arguments_without_gpu(lib):
     so.workers = 0
     so.match.validate = 1
     assert lib.hgm_server_create(0x1000, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    so.match.validate = 0
+    so.edge_side_only = 2
+    assert lib.hgm_server_create(0x1000, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
+    so.edge_side_only = 1
+    so.match.variant = hgm.VARIANTS["crew"]
+    assert lib.hgm_server_create(0x1000, 1 << 20, ctypes.byref(so), ctypes.byref(h)) == hgm.HGM_E_ARG
     assert lib.hgm_server_submit(None, None) == hgm.HGM_E_ARG
     assert lib.hgm_server_poll(None, None, 0, 0.0) == hgm.HGM_E_ARG
     assert lib.hgm_server_info(None, None) == hgm.HGM_E_ARG

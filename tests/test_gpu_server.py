@@ -48,13 +48,19 @@ def test_mix_equals_alone_and_oracle(hgm, pool):
     exp = _expected(pool)
     srv = hgm.Server(1 << 30, workers=2)
     try:
-        # a first burst, then late arrivals while the first waves are running
+        # warm-up: the workers' first device calls happen here
+        srv.submit(pool[0], 1, req_id=10_000)
+        _drain(srv, 1)
+        # a first burst; once it has been admitted as a wave, the rest arrive
+        # and form a second wave while the first is still on the device
         for i in range(24):
             srv.submit(pool[i], 1000 + i, req_id=i)
-        time.sleep(0.002)
+        t0 = time.time()
+        while srv.info()["queued"] > 0:
+            assert time.time() - t0 < 30, "first wave never admitted"
+            time.sleep(0.0001)
         for i in range(24, len(pool)):
             srv.submit(pool[i], 1000 + i, req_id=i)
-            time.sleep(0.0005)
         res = _drain(srv, len(pool))
         info = srv.info()
     finally:
@@ -114,3 +120,18 @@ def test_request_larger_than_budget_fails_cleanly(hgm, pool):
     assert res[1]["status"] == 0
     exp = oracle.greedy(small.n, small.m, small.e_off, small.e_pins, small.w, 2)[0]
     assert np.array_equal(res[1]["bits"], exp)
+
+
+def test_edge_side_only_requests(hgm, pool):
+    """Requests without the vertex side (not uploaded): same bitmaps."""
+    exp = _expected(pool)
+    srv = hgm.Server(1 << 30, workers=3, edge_side_only=True)
+    try:
+        for i, g in enumerate(pool):
+            srv.submit(g, 1000 + i, req_id=i)
+        res = _drain(srv, len(pool))
+    finally:
+        srv.close()
+    assert all(r["status"] == 0 for r in res)
+    for r in res:
+        assert np.array_equal(r["bits"], exp[r["id"]]), f"request {r['id']} differs"
