@@ -289,14 +289,15 @@ def cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(g, seed, budget_s):
+def cpu_baseline(g, seed, budget_s, reseed=False):
     import numpy as np
     import oracle
     t0 = time.perf_counter()
     runs = 0
     stats = None
     while True:
-        _, stats = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed)
+        _, stats = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed,
+                                    reseed=reseed)
         runs += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -312,16 +313,17 @@ def cpu_baseline(g, seed, budget_s):
                        f"oracle greedy on the same input: {tg:.3f} s")}
 
 
-def cpu_multicore(g, seed, budget_s):
+def cpu_multicore(g, seed, budget_s, reseed=False):
     """The OpenMP local max (baselines/) on the host's cores, full workload."""
     import baselines
     threads = max(1, min(16, os.cpu_count() or 1))
-    baselines.local_max(g.n, g.m, g.e_off, g.e_pins, g.w, seed, threads=threads)   # warm-up
+    baselines.local_max(g.n, g.m, g.e_off, g.e_pins, g.w, seed, reseed=reseed,
+                        threads=threads)   # warm-up
     t0 = time.perf_counter()
     runs = 0
     while True:
         _, rounds, sum_k = baselines.local_max(g.n, g.m, g.e_off, g.e_pins, g.w, seed,
-                                               threads=threads)
+                                               reseed=reseed, threads=threads)
         runs += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -340,6 +342,8 @@ def main():
     ap.add_argument("--workload", default="power-law", choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto", choices=["auto", "crcw", "crew"])
     ap.add_argument("--rounds-per-sync", type=int, default=0)
+    ap.add_argument("--reseed", type=int, default=0,
+                    help="1: priorities drawn afresh every round (the paper's per-round noise)")
     ap.add_argument("--hub-threshold", type=int, default=0,
                     help="degree above which a vertex is split into pieces (0 = library default)")
     ap.add_argument("--cpu-baseline", type=float, default=10.0,
@@ -397,7 +401,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     opts = hgm.make_opts(args.variant, rounds_per_sync=args.rounds_per_sync, pairs=pairs,
-                         hub_threshold=args.hub_threshold)
+                         hub_threshold=args.hub_threshold, reseed=bool(args.reseed))
     ws = hgm.alloc_workspace(dg, opts)
     bits = torch.empty(max((g.m + 31) // 32, 1), dtype=torch.int32, device=dev)
     torch.cuda.synchronize()
@@ -464,6 +468,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "n": g.n, "m": g.m, "kappa": g.kappa,
                    "variant": args.variant, "hub_threshold": args.hub_threshold or None,
+                   "reseed": bool(args.reseed),
                    "rounds": st["rounds"],
                    "sum_kappa_r": sum_k, "matched": st["matched"]},
         "input_incidences_per_s": g.kappa / t_step,
@@ -496,9 +501,9 @@ def main():
                                       args.serve_budget_gb, args.serve_workers,
                                       edge_side_only=not args.serve_vertex_side)
     if args.cpu_baseline > 0:
-        result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline)
+        result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline, bool(args.reseed))
     if args.cpu_multicore > 0:
-        result["cpu_multicore"] = cpu_multicore(g, seed, args.cpu_multicore)
+        result["cpu_multicore"] = cpu_multicore(g, seed, args.cpu_multicore, bool(args.reseed))
     print(json.dumps(result), flush=True)
 
 

@@ -273,7 +273,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
         if (i < g.m && (flags & kInitLiveKey))
-            s.live_key[i] = s.key ? edge_key<true>(g, s, seed, (int)i) : edge_key<false>(g, s, seed, (int)i);
+            s.live_key[i] = s.key ? edge_key<true>(g, s, seed, (int)i)
+                                  : edge_key<false>(g, s, seed, (int)i);
         if (i < g.n) {
             s.best[0][i] = 0;
             s.done[i] = 0;
