@@ -14,7 +14,7 @@ using namespace hgm;
 
 namespace {
 
-constexpr int kFirstBatch = 4;         // rounds enqueued before the first termination check
+constexpr int kFirstBatch = 4;         // fewest rounds enqueued before the first termination check
 constexpr int kAdaptiveMaxBatch = 32;  // cap of a predicted batch
 constexpr int kMaxRoundsPerSync = 200;
 constexpr int kDefaultHubThreshold = 8192;
@@ -168,16 +168,22 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     return s;
 }
 
-// Rounds to enqueue before the next termination check.  Live pins shrink by a
-// factor per round that grows as the instance thins out, so with the latest
-// factor f the rounds left are at most about log(kappa_r) / log(f); a little
-// over half of that, plus the retire pass that finds the live set empty,
-// matched the measured round counts.  An unneeded round costs two
-// near-empty launches (a few microseconds each), a missing one a further host
-// round trip (tens of microseconds).
+// Rounds to enqueue before the next termination check.  The first batch is
+// sized from kappa: about 0.4 log2(kappa) rounds covered the measured round
+// counts of hash-ordered instances (6 at kappa = 1.4e5 to 11 at 4.8e8)
+// within two.  Afterwards live pins shrink by a factor per round that grows
+// as the instance thins out, so with the latest factor f the rounds left are
+// at most about log(kappa_r) / log(f); a little over half of that, plus the
+// retire pass that finds the live set empty, matched the measured counts.
+// An unneeded round costs two near-empty launches (about 10 us), a missing
+// one a further host round trip (about 45 us).
 int next_batch(const Opts &o, int launched, const std::vector<int64_t> &live_pins) {
     if (!o.adaptive) return o.rounds_per_sync;
-    if (launched == 0 || live_pins.size() < 2) return kFirstBatch;
+    if (launched == 0 || live_pins.size() < 2) {
+        const double k0 = live_pins.empty() ? 2.0 : std::max<double>(2.0, (double)live_pins[0]);
+        const int first = (int)std::lround(0.4 * std::log2(k0));
+        return std::max(kFirstBatch, std::min(kAdaptiveMaxBatch, first));
+    }
     const double cur = (double)live_pins.back();
     const double prev = (double)live_pins[live_pins.size() - 2];
     if (cur <= 1.0) return 2;
@@ -297,7 +303,9 @@ struct KernelTimer {
         return hipEventRecord(e, stream);
     }
     // After a stream synchronisation: add the bracketed durations of kernels
-    // of rounds < live_rounds (round -1 = setup) and restart from the last event.
+    // of rounds < live_rounds (round -1 = setup).  The next bracket starts
+    // at resume(), so the host's time between batches is not charged to the
+    // next batch's first kernel.
     hipError_t harvest(int live_rounds, hgm_stats *st, std::vector<float> &round_ms) {
         if (!on) return hipSuccess;
         auto &p = pool();
@@ -314,11 +322,19 @@ struct KernelTimer {
                 round_ms[r] += ms;
             }
         }
-        std::swap(p[0], p[used - 1]);
-        used = 1;
+        used = 0;
         cls.clear();
         round.clear();
         return hipSuccess;
+    }
+    // Records a start event when the previous ones were harvested.
+    hipError_t resume() {
+        if (!on || used > 0) return hipSuccess;
+        hipEvent_t e;
+        hipError_t rc = event(0, &e);
+        if (rc != hipSuccess) return rc;
+        used = 1;
+        return hipEventRecord(e, stream);
     }
 };
 
@@ -371,6 +387,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     int max0_event = -1;  // timer entry of the AUTO round-0 maximum (class fixed after the sync)
     bool finished = g.m == 0;
     if (!finished) {
+        HGM_TRY(T.resume());
         if (o.variant == HGM_VARIANT_AUTO && o.have_vertex_side) {
             HGM_TRY(launch_max0(L, g, s, kseed(0)));
             max0_event = (int)T.cls.size();
@@ -400,6 +417,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
         if (o.max_rounds > 0) batch = std::min(batch, o.max_rounds - launched);
         if (batch <= 0) return HGM_E_ROUND_LIMIT;
         const int first = launched;
+        HGM_TRY(T.resume());
         for (int b = 0; b < batch; ++b) {
             const int r = launched;
             const bool next_crew = crew_round(o, r + 1);
