@@ -268,7 +268,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     __shared__ unsigned long long sum_tmp[kWaves];
     unsigned long long hot = 0;
     const int64_t words = g.words;
-    const int64_t span = g.m > g.n ? g.m : g.n;
+    const int64_t edges = (flags & kInitLiveKey) ? g.m : 0;  // edge-indexed work: live keys only
+    const int64_t span = edges > g.n ? edges : g.n;
     const int64_t top = span > words ? span : words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
