@@ -17,15 +17,17 @@
  * the given seed.  H is a bijection of e for a fixed seed, so keys are
  * distinct and the id never decides.  With a fixed strict order the local-max
  * rounds select exactly the matching that sequential greedy selects in that
- * order, so there is one correct output per (instance, seed).
+ * order, so there is one correct output per (instance, seed).  opts->reseed
+ * instead draws the tie-breaking priority afresh every round.
  *
  * Conventions for every entry point:
  *  - All array pointers inside hgm_csr, the output bitmap and the workspace
  *    are DEVICE pointers owned by the caller; the library allocates nothing.
  *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
- *    it; hgm_match synchronises that stream at least once every
- *    opts->rounds_per_sync rounds to test for termination, and returns when
- *    the matching is complete in device memory.
+ *    it in batches of rounds (opts->rounds_per_sync rounds, or a number the
+ *    library predicts from the instance when that is 0); the stream is
+ *    synchronised after each batch to test for termination, and the call
+ *    returns when the matching is complete in device memory.
  *  - Return value: HGM_OK (0) or a negative HGM_E_* code; no exception or
  *    abort crosses this interface.  hgm_strerror() describes a code.
  *  - Calls that share a workspace must not overlap.
@@ -62,9 +64,10 @@ extern "C" {
  *                        the exact transpose of e_pins (any order inside a list)
  *   w       uint32[m]   edge weights (0 allowed)
  * Empty edges (size 0) are allowed and are matched (they conflict with
- * nothing); degree-0 vertices are allowed.  v_off/v_edges are read only by
- * the CREW variant and by validation; they may be NULL when opts->variant is
- * HGM_VARIANT_CRCW and validation is off. */
+ * nothing); degree-0 vertices are allowed.  v_off/v_edges are required by
+ * the CREW variant and by validation; AUTO uses them when given (round-0
+ * form, hub pieces) and runs the edge-centric form without them; CRCW never
+ * reads them.  Both may then be NULL. */
 typedef struct hgm_csr {
     int32_t n, m;
     int64_t kappa;
@@ -78,8 +81,11 @@ typedef struct hgm_csr {
 /* Options; a NULL pointer means all defaults (the value 0 of each field). */
 typedef struct hgm_opts {
     int32_t variant;         /* HGM_VARIANT_*; 0 = AUTO */
-    int32_t hub_threshold;   /* CREW: vertices of larger degree are split over
-                                several workgroups; 0 = library default */
+    int32_t hub_threshold;   /* vertices of larger degree are hubs: the
+                                vertex-centric passes split their lists over
+                                several workgroups, and AUTO's round-0 edge
+                                scatter reduces their pins per workgroup in
+                                LDS; 0 = library default (8192) */
     int32_t rounds_per_sync; /* rounds enqueued between host termination checks;
                                 0 = library default */
     int32_t validate;        /* 1 = check the input first (extra O(kappa d) work
@@ -105,7 +111,7 @@ typedef struct hgm_opts {
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */
-#define HGM_K_SETUP 0      /* key construction, validation, hub list */
+#define HGM_K_SETUP 0      /* state clearing, batch keys, validation, hub pieces */
 #define HGM_K_SCATTER 1    /* round-0 edge-centric maximum (CRCW) */
 #define HGM_K_VERTEX_MAX 2 /* vertex-centric maximum (CREW) */
 #define HGM_K_TEST 3       /* local-max test and marking */
@@ -219,10 +225,11 @@ typedef struct hgm_request {
     int64_t id;              /* caller's tag, echoed in the result */
     int32_t n, m;
     int64_t kappa;
-    const int32_t *e_off;    /* HOST arrays in the hgm_csr layout (vertex side */
-    const int32_t *e_pins;   /* required); they must stay valid until the */
-    const int32_t *v_off;    /* request's result has been polled.  Pinned */
-    const int32_t *v_edges;  /* host memory makes the uploads asynchronous. */
+    const int32_t *e_off;    /* HOST arrays in the hgm_csr layout (the vertex */
+    const int32_t *e_pins;   /* side is required unless edge_side_only); they */
+    const int32_t *v_off;    /* must stay valid until the request's result has */
+    const int32_t *v_edges;  /* been polled.  Pinned host memory makes the */
+                             /* uploads asynchronous. */
     const uint32_t *w;
     uint32_t seed;
     uint32_t *bits_out;      /* HOST, ceil(m/32) words, written before the result is posted */

@@ -499,7 +499,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
 
 extern "C" {
 
-int hgm_version(void) { return 200; }
+int hgm_version(void) { return 300; }
 
 const char *hgm_strerror(int code) {
     switch (code) {

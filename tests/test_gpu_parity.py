@@ -298,3 +298,39 @@ def test_hub_stress_full(hgm, hub_stress, variant):
     g, ex = hub_stress
     print(f"hub-stress full n={g.n} m={g.m} kappa={g.kappa} variant={variant}", flush=True)
     _check(hgm, g, 1, variant, expect=ex)
+
+
+def test_concurrent_calls_on_two_streams(hgm):
+    """Two host threads call hgm_match at once, each on its own stream and
+    workspace (with per-kernel timing on, which keeps a per-thread event
+    pool): every result equals the oracle's."""
+    import threading
+    import torch
+    gs = [synth.random_instance(400 + i, 20_000, 60_000, 2, 10, 1, 50) for i in range(2)]
+    exp = [oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, 9)[0] for g in gs]
+    dgs = [hgm.DeviceHypergraph.from_host(g, "cuda:0") for g in gs]
+    errors = []
+
+    def worker(i):
+        try:
+            stream = torch.cuda.Stream()
+            opts = hgm.make_opts("auto")
+            ws = hgm.alloc_workspace(dgs[i], opts)
+            for _ in range(20):
+                bits, st = hgm.match(dgs[i], 9, opts, workspace=ws, stream=stream.cuda_stream,
+                                     timing=True)
+                stream.synchronize()
+                got = bits.cpu().numpy().view(np.uint32)
+                if not np.array_equal(got, exp[i]):
+                    errors.append(f"thread {i}: bitmap differs")
+                    return
+        except Exception as ex:   # reported below, on the main thread
+            errors.append(f"thread {i}: {ex!r}")
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
