@@ -907,36 +907,73 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
     }
 }
 
-// Batch setup (one workgroup per instance): global pin and incidence
-// offsets, per-edge vertex base and bitmap offset, per-vertex edge base, and
-// keys w << 32 | H(seed_i, local id) with each instance's own seed.  Each
-// instance's bitmap starts at bit 32 * word_base[i].
+// Batch setup: global pin and incidence offsets, per-edge vertex base and
+// bitmap offset, per-vertex edge base, and keys w << 32 | H(seed_i, local id)
+// with each instance's own seed.  Each instance's bitmap starts at bit
+// 32 * word_base[i].  Work is balanced over items, not instances (instance
+// sizes span orders of magnitude): workgroup b takes the b-th contiguous
+// range of edges, then of vertices; one binary search finds the instance at
+// the range's start, and each lane moves forward over instance boundaries as
+// its item advances through the range.
+
+// Largest i in [0, count) with base[i] <= x: the instance holding item x
+// (base non-decreasing, base[0] = 0, base[count] > x; empty instances are
+// skipped because a later instance with the same base is larger).
+__device__ __forceinline__ int instance_of(const int64_t *base, int count, int64_t x) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// This workgroup's range [lo, hi) of `total` items, a multiple of kBlock long.
+__device__ __forceinline__ void block_range(int64_t total, int64_t *lo, int64_t *hi) {
+    const int64_t per =
+        ((total + gridDim.x - 1) / gridDim.x + kBlock - 1) / kBlock * kBlock;
+    *lo = (int64_t)blockIdx.x * per;
+    *hi = *lo + per < total ? *lo + per : total;
+}
+
 __global__ void __launch_bounds__(kBlock) k_batch_setup(Graph g, BatchIn b, State s) {
-    for (int i = blockIdx.x; i < b.count; i += gridDim.x) {
-        const int64_t eb = b.e_base[i], ne = b.e_base[i + 1] - eb;
-        const int64_t vb = b.v_base[i], nv = b.v_base[i + 1] - vb;
-        const int64_t pb = b.pin_base[i];
-        const int64_t wb = b.word_base[i];
-        const uint32_t seed = b.seeds[i];
-        const int32_t *eo = b.e_off + eb + i;
-        for (int64_t el = threadIdx.x; el < ne; el += kBlock) {
-            const int64_t e = eb + el;
-            b.goff[e] = (int32_t)(pb + eo[el]);
-            b.vbase[e] = (int32_t)vb;
-            b.bitoff[e] = (int32_t)(32 * wb - eb);
-            s.key[e] = ((uint64_t)g.w[e] << 32) | priority_hash(seed, (uint32_t)el);
+    __shared__ int first;
+    int64_t lo, hi;
+    block_range(g.m, &lo, &hi);
+    if (lo < hi) {
+        if (threadIdx.x == 0) first = instance_of(b.e_base, b.count, lo);
+        __syncthreads();
+        int i = first;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock) {
+            while (i + 1 < b.count && b.e_base[i + 1] <= e) ++i;
+            const int64_t eb = b.e_base[i], el = e - eb;
+            b.goff[e] = (int32_t)(b.pin_base[i] + b.e_off[eb + i + el]);
+            b.vbase[e] = (int32_t)b.v_base[i];
+            b.bitoff[e] = (int32_t)(32 * b.word_base[i] - eb);
+            s.key[e] = ((uint64_t)g.w[e] << 32) | priority_hash(b.seeds[i], (uint32_t)el);
         }
-        if (b.gvoff) {
-            const int32_t *vo = b.v_off + vb + i;
-            for (int64_t vl = threadIdx.x; vl < nv; vl += kBlock) {
-                b.gvoff[vb + vl] = (int32_t)(pb + vo[vl]);
-                b.ebase[vb + vl] = (int32_t)eb;
+        __syncthreads();  // `first` is reused below
+    }
+    if (b.gvoff) {
+        block_range(g.n, &lo, &hi);
+        if (lo < hi) {
+            if (threadIdx.x == 0) first = instance_of(b.v_base, b.count, lo);
+            __syncthreads();
+            int i = first;
+            for (int64_t v = lo + threadIdx.x; v < hi; v += kBlock) {
+                while (i + 1 < b.count && b.v_base[i + 1] <= v) ++i;
+                const int64_t vb = b.v_base[i];
+                b.gvoff[v] = (int32_t)(b.pin_base[i] + b.v_off[vb + i + (v - vb)]);
+                b.ebase[v] = (int32_t)b.e_base[i];
             }
         }
-        if (i == b.count - 1 && threadIdx.x == 0) {
-            b.goff[g.m] = (int32_t)b.pin_base[b.count];
-            if (b.gvoff) b.gvoff[g.n] = (int32_t)b.pin_base[b.count];
-        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        b.goff[g.m] = (int32_t)b.pin_base[b.count];
+        if (b.gvoff) b.gvoff[g.n] = (int32_t)b.pin_base[b.count];
     }
 }
 
@@ -956,9 +993,8 @@ hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const Sta
 }
 
 hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s) {
-    const int grid = b.count < L.grid ? b.count : L.grid;
-    if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_setup, dim3(grid), dim3(kBlock), 0, L.stream, g, b, s);
+    if (b.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_setup, dim3(L.grid), dim3(kBlock), 0, L.stream, g, b, s);
     return hipGetLastError();
 }
 
