@@ -203,7 +203,7 @@ def batched_leg(count, steps):
             "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same}
 
 
-def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2,
+def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
                edge_side_only=True):
     """Open-loop Poisson arrivals at `rate` req/s for `duration` s into the
     request server.  Requests are drawn (seeded) from a pool of pre-generated
@@ -211,7 +211,7 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2,
     |e| ~ U{2..32}, m = round(kappa/17), n = max(32, round(m/2)),
     w ~ U{1..1e6}); request i uses priority seed i.  Latency = completion
     minus scheduled arrival (monotonic clock), over requests arriving after
-    the first `warmup_frac` of the run."""
+    the first `warmup_s` seconds (at most a fifth of the run)."""
     import threading
     import numpy as np
     import torch
@@ -264,7 +264,7 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_frac=0.2,
     srv.close()
     end = max(r["t_done"] for r in done)
     ok = [r for r in done if r["status"] == 0]
-    lat = np.array([r["t_done"] - sched[r["id"]] for r in ok if arrivals[r["id"]] >= warmup_frac * duration])
+    lat = np.array([r["t_done"] - sched[r["id"]] for r in ok if arrivals[r["id"]] >= min(warmup_s, 0.2 * duration)])
     kap = sum(views[pick[r["id"]]].kappa for r in ok)
     return {"rate": rate, "duration_s": duration, "requests": int(arrivals.size),
             "completed": len(ok), "failed": len(done) - len(ok), "pool": pool_count,
@@ -352,7 +352,7 @@ def main():
                     help="seconds of the multicore CPU local max baseline (0 = skip)")
     ap.add_argument("--batch-count", type=int, default=4096,
                     help="instances in the batched-vs-plain leg (0 = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the served leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-pool", type=int, default=48)
