@@ -220,7 +220,9 @@ int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace,
  * which another worker runs concurrently.  A wave's memory returns to the
  * arena when it completes, admitting waiting requests.  A request's bitmap is
  * exactly hgm_match's for that instance and seed, whatever it ran with.  A
- * request larger than the whole arena completes with status HGM_E_SIZE. */
+ * request larger than the whole arena completes with status HGM_E_SIZE.  A
+ * wave also stays within hgm_match_batch's 32-bit totals (n, m, kappa and
+ * 32 * bitmap words below 2^31). */
 typedef struct hgm_request {
     int64_t id;              /* caller's tag, echoed in the result */
     int32_t n, m;
@@ -261,10 +263,13 @@ typedef struct hgm_server_state {
 typedef struct hgm_server hgm_server;
 
 /* arena: device memory, 256-byte aligned, owned by the caller and unused by
- * it until hgm_server_destroy returns.  The current device is the server's. */
+ * it until hgm_server_destroy returns.  The current device is the server's.
+ * HGM_E_HIP when the workers' streams cannot be created. */
 int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *opts,
                       hgm_server **out);
-/* Queues a request (non-blocking, thread-safe). */
+/* Queues a request (non-blocking, thread-safe).  HGM_E_ARG for negative
+ * sizes, kappa >= 2^31 or a NULL array that its sizes require; HGM_E_SIZE when
+ * its bitmap alone exceeds a wave's limit (m > 2^31 - 32). */
 int hgm_server_submit(hgm_server *server, const hgm_request *req);
 /* Moves up to `cap` finished results to `out`, waiting up to timeout_s
  * seconds for the first; returns how many were written (or an HGM_E_* code). */

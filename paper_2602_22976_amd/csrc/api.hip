@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -249,16 +250,19 @@ int check_graph(const hgm_csr *g, const Opts &o) {
 }
 
 int device_grid() {
-    static int cached[64] = {0};
+    static std::atomic<int> cached[64];  // zero-initialised (static storage)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    if (dev >= 0 && dev < 64) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c) return c;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         return 0;
     int grid = cus * kBlocksPerCu;
-    if (dev >= 0 && dev < 64) cached[dev] = grid;
+    if (dev >= 0 && dev < 64) cached[dev].store(grid, std::memory_order_relaxed);
     return grid;
 }
 

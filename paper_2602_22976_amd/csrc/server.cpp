@@ -109,6 +109,7 @@ struct hgm_server {
     bool stopping = false;
     bool forming = false;  // one worker at a time forms a wave, in arrival order
     std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;  // one per worker
     int64_t submitted = 0, completed = 0;
 
     hgm_server(char *base, size_t bytes) : arena_base(base), arena(bytes) {}
@@ -158,6 +159,10 @@ WaveLayout wave_layout(int count, int64_t n, int64_t m, int64_t kappa, int64_t w
 }
 
 size_t words_of(int32_t m) { return ((size_t)m + 31) / 32; }
+
+// A wave is one hgm_match_batch call, whose totals of vertices, edges, pins
+// and bitmap bits are 32-bit.
+constexpr int64_t kWaveLimit = ((int64_t)1 << 31) - 1;
 
 void finish(hgm_server *S, const std::vector<Pending> &wave, int status, double t_admit) {
     const double t = now_s();
@@ -265,10 +270,8 @@ int run_wave(hgm_server *S, hipStream_t stream, const std::vector<Pending> &wave
     return HGM_OK;
 }
 
-void worker_main(hgm_server *S) {
-    if (hipSetDevice(S->device) != hipSuccess) return;
-    hipStream_t stream = nullptr;
-    if (hipStreamCreate(&stream) != hipSuccess) return;
+void worker_main(hgm_server *S, hipStream_t stream) {
+    (void)hipSetDevice(S->device);  // checked by hgm_server_create on this device
     const int max_batch = S->opts.max_batch;
     for (;;) {
         std::vector<Pending> wave;
@@ -290,6 +293,10 @@ void worker_main(hgm_server *S) {
                 size_t best = 0;
                 for (size_t i = 0; i < S->queue.size() && (int)wave.size() < max_batch; ++i) {
                     const hgm_request &q = S->queue[i].req;
+                    if (n + q.n > kWaveLimit || m + q.m > kWaveLimit ||
+                        kappa + q.kappa > kWaveLimit ||
+                        32 * (words + (int64_t)words_of(q.m)) > kWaveLimit)
+                        break;  // submit checked that each request fits alone
                     const WaveLayout T = wave_layout((int)wave.size() + 1, n + q.n, m + q.m,
                                                      kappa + q.kappa,
                                                      words + (int64_t)words_of(q.m), S->opts);
@@ -343,7 +350,6 @@ void worker_main(hgm_server *S) {
         S->cv_work.notify_all();
         finish(S, wave, rc, t_admit);
     }
-    (void)hipStreamDestroy(stream);
 }
 
 }  // namespace
@@ -365,10 +371,19 @@ int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *op
     if (o.max_batch == 0) o.max_batch = 1024;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return HGM_E_HIP;
+    // The workers' streams, created here so that a failure is reported.
+    std::vector<hipStream_t> streams(o.workers, nullptr);
+    for (int i = 0; i < o.workers; ++i) {
+        if (hipStreamCreate(&streams[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipStreamDestroy(streams[j]);
+            return HGM_E_HIP;
+        }
+    }
     hgm_server *S = new hgm_server((char *)arena, arena_bytes);
     S->opts = o;
     S->device = dev;
-    for (int i = 0; i < o.workers; ++i) S->workers.emplace_back(worker_main, S);
+    S->streams = streams;
+    for (int i = 0; i < o.workers; ++i) S->workers.emplace_back(worker_main, S, streams[i]);
     *out = S;
     return HGM_OK;
 }
@@ -377,6 +392,7 @@ int hgm_server_submit(hgm_server *S, const hgm_request *req) {
     if (!S || !req) return HGM_E_ARG;
     const hgm_request &q = *req;
     if (q.n < 0 || q.m < 0 || q.kappa < 0 || q.kappa >= ((int64_t)1 << 31)) return HGM_E_ARG;
+    if (32 * (int64_t)words_of(q.m) > kWaveLimit) return HGM_E_SIZE;
     if ((q.m > 0 && (!q.e_off || !q.w || !q.bits_out)) || (q.kappa > 0 && !q.e_pins))
         return HGM_E_ARG;
     if (!S->opts.edge_side_only && (!q.v_off || (q.kappa > 0 && !q.v_edges))) return HGM_E_ARG;
@@ -422,6 +438,7 @@ int hgm_server_destroy(hgm_server *S) {
     }
     S->cv_work.notify_all();
     for (auto &t : S->workers) t.join();
+    for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
     delete S;
     return HGM_OK;
 }

@@ -135,3 +135,31 @@ def test_edge_side_only_requests(hgm, pool):
     assert all(r["status"] == 0 for r in res)
     for r in res:
         assert np.array_equal(r["bits"], exp[r["id"]]), f"request {r['id']} differs"
+
+
+def test_submit_argument_errors(hgm):
+    """Requests the server refuses at submit, through the C ABI: nothing is
+    queued and the server keeps serving."""
+    import ctypes
+    lib = hgm.load()
+    srv = hgm.Server(1 << 20, workers=1)
+    try:
+        def submit(**kw):
+            q = hgm.HgmRequest()
+            q.id, q.n, q.m, q.kappa = 0, 0, 0, 0
+            for k, v in kw.items():
+                setattr(q, k, v)
+            return lib.hgm_server_submit(srv.h, ctypes.byref(q))
+        assert submit(n=-1) == hgm.HGM_E_ARG
+        assert submit(kappa=1 << 31) == hgm.HGM_E_ARG
+        assert submit(m=3, n=2) == hgm.HGM_E_ARG            # arrays missing
+        assert submit(m=2 ** 31 - 1) == hgm.HGM_E_SIZE      # its bitmap exceeds a wave's bits
+        assert lib.hgm_server_submit(None, None) == hgm.HGM_E_ARG
+        assert srv.info()["submitted"] == 0
+        g = synth.random_instance(3, 50, 40, 2, 5, 1, 9)
+        srv.submit(g, 4, req_id=7)
+        (r,) = _drain(srv, 1)
+    finally:
+        srv.close()
+    assert r["status"] == 0
+    assert np.array_equal(r["bits"], oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, 4)[0])
