@@ -13,8 +13,10 @@ Printed (one JSON line):
                work_inflation = sum kappa_r / kappa; kernel_incidences_per_s
                = sum kappa_r over the summed kernel time
   roofline     the dominant kernel's algorithmic bytes / its HIP-event time,
-               against the 8 TB/s HBM peak; `traffic` from the committed
-               rocprofv3 PMC summary when it matches the kernel source
+               against the 8 TB/s HBM peak; `traffic` (bytes per launch) from
+               the committed rocprofv3 PMC summary when it matches the kernel
+               source, and traffic_gbs / traffic_frac, that traffic over the
+               same average launch time
   cpu_baseline the oracle's round simulator on the host (one core), same unit
   cpu_multicore the OpenMP local max of baselines/ on the host's cores (up
                to 16 threads), same unit
@@ -452,6 +454,11 @@ def main():
     achieved = model[dom] / (dom_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
     traffic = load_traffic(args.workload, dom, digest, dom_launch)
+    # Measured traffic rate: calibrated L2-to-fabric bytes per launch over the
+    # average launch time (fabric bytes include Infinity Cache hits, so this
+    # bounds the DRAM rate from above).
+    traffic_gbs = (traffic / (dom_ms / dom_launch * 1e-3) / 1e9
+                   if traffic is not None and dom_launch else None)
 
     result = {
         "metric": METRIC,
@@ -474,6 +481,8 @@ def main():
         "input_incidences_per_s": g.kappa / t_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": traffic_gbs,
+                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs else None,
                      "kernel": dom, "launches_per_step": dom_launch,
                      "ms_per_step": dom_ms, "algorithmic_bytes_per_step": model[dom],
                      "kernel_source": digest},
