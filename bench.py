@@ -60,23 +60,31 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(stats, variant_rounds, n, pairs=False):
+def algorithmic_bytes(stats, variant_rounds, n, pairs=False, reseed=False):
     """Bytes each kernel class must move, from the per-round counts.
 
     Units per round r: E = live edges, K = their pins, M / P = matched edges
     and their pins, E' / K' = survivors into round r+1.  Counts each array
     element the step needs once (re-reads from cache are not algorithmic).
-    A key is rebuilt from the 4-byte weight and the hash, never stored.  With
-    the pair layout (graphs) no edge offsets are read (4 B less per edge in
-    round 0's scatter, 8 B less per edge in every test and retire):
+    One instance stores no per-edge key: round 0 rebuilds it from the 4-byte
+    weight and the hash.  From round 1 on, each live-list slot carries the
+    edge's record beside its id (pin offset 4 + pin count 4 + first pin 4,
+    or the two pins 8 with the pair layout, and the round's key 8), written
+    by the retire pass for every survivor.  With the pair layout (graphs) no
+    edge offsets are read:
       scatter (round 0): 8 B/edge (offset 4, weight 4) + 12 B/pin (pin 4,
               atomic 8)
-      test:   per edge id 4 (not in round 0) + offsets 8 + weight 4, per pin
-              pin 4 + best 8 (+ 8 clearing next round's buffer in CRCW),
-              per matched edge 4 (bitmap) and per matched pin 1 (done)
-      retire: per edge id 4 (not in round 0) + offsets 8, per pin pin 4 +
-              done 1, per survivor id write 4 (+ weight 4 and 8 per surviving
-              pin for the fused CRCW scatter; CREW: 8 per dead edge key)
+      test:   per edge: round 0 offsets 8 + weight 4; later rounds id 4 +
+              offset and count 8 + key 8 (the first pin comes from the
+              record and counts as a pin).  Per pin: pin 4 + best 8 (+ 8
+              clearing next round's buffer in CRCW); per matched edge 4
+              (bitmap) and per matched pin 1 (done)
+      retire: per edge: id 4 (not in round 0) + offset and count 8; per
+              pin: pin 4 + done 1; per survivor: id 4 + record written
+              (12 + key 8, pair layout 8 + 8) + its key read (weight 4 in
+              round 0 or with per-round priorities, else the record's 8).
+              CRCW adds 8 per surviving pin for the fused scatter; CREW 8
+              per dead edge key
       vertex max: round 0 per vertex done 1 + offsets 4 + best 8, per pin
               v_edges 4 + weight 4.  Later rounds (CREW variant) read the
               lists compacted one round earlier: per vertex 21 (adds the list
@@ -90,11 +98,11 @@ def algorithmic_bytes(stats, variant_rounds, n, pairs=False):
     P = stats["matched_pins"]
     R = stats["rounds"]
     out = {"scatter": 0.0, "test": 0.0, "retire": 0.0, "vertex_max": 0.0}
-    offb = 0 if pairs else 8   # e_off[e], e_off[e + 1] per edge
+    offb = 0 if pairs else 8   # e_off[e], e_off[e + 1] per edge (record: offset, count)
+    recw = 8 + 8 if pairs else 12 + 8   # record written per survivor, key included
     for r in range(R):
         crew_r = variant_rounds(r)
         crew_next = variant_rounds(r + 1)
-        idb = 0 if r == 0 else 4
         if r == 0 and not crew_r:
             out["scatter"] += (offb // 2 + 4) * E[0] + 12 * K[0]
         if crew_r:
@@ -102,12 +110,14 @@ def algorithmic_bytes(stats, variant_rounds, n, pairs=False):
                 out["vertex_max"] += 13 * n + 8 * K[0]
             else:
                 out["vertex_max"] += 21 * n + 12 * K[r - 1] + 4 * K[r]
-        out["test"] += (idb + offb + 4) * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
-        ret = (idb + offb) * E[r] + 5 * K[r] + 4 * E[r + 1]
+        test_edge = offb + 4 if r == 0 else 4 + offb + 8
+        out["test"] += test_edge * E[r] + (12 + (0 if crew_next else 8)) * K[r] + 4 * M[r] + P[r]
+        keysrc = 4 if (r == 0 or reseed) else 8
+        ret = ((0 if r == 0 else 4) + offb) * E[r] + 5 * K[r] + (4 + recw + keysrc) * E[r + 1]
         if crew_next:
             ret += 8 * (E[r] - E[r + 1])
         else:
-            ret += 4 * E[r + 1] + 8 * K[r + 1]
+            ret += 8 * K[r + 1]
         out["retire"] += ret
     return out
 
@@ -446,7 +456,8 @@ def main():
 
     crew_all = args.variant == "crew"
     crew0 = crew_all or launches.get("vertex_max", 0) > 0   # AUTO's round-0 form
-    model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n, pairs)
+    model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n, pairs,
+                              bool(args.reseed))
     cand = {k: tot_ms[k] for k in model if tot_ms.get(k, 0) > 0}
     dom = max(cand, key=cand.get)
     dom_ms = tot_ms[dom] / args.steps

@@ -33,7 +33,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
-    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, stats, err, live_key, vedges0,
+    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
         piece_count, hot, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
@@ -114,6 +114,13 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     L.list1 = take(4 * cap);
     L.cnt0 = take(4 * (size_t)L.grid);
     L.cnt1 = take(4 * (size_t)L.grid);
+    for (int k = 0; k < 2; ++k) {
+        L.rec[k][0] = take(4 * cap);                 // rec_a
+        L.rec[k][1] = take(4 * cap);                 // rec_b
+        L.rec[k][2] = take(4 * cap);                 // rec_c
+        L.rec[k][3] = take(batch ? 4 * cap : 0);     // rec_vb
+        L.rec[k][4] = take(8 * cap);                 // rec_key
+    }
     L.stats = take(sizeof(RoundStats) * (size_t)L.ring);
     L.err = take(4);
     L.live_key = take(uses_live_key(o) ? 8 * (size_t)m : 0);
@@ -153,6 +160,13 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.list[1] = (int32_t *)(b + L.list1);
     s.cnt[0] = (int32_t *)(b + L.cnt0);
     s.cnt[1] = (int32_t *)(b + L.cnt1);
+    for (int k = 0; k < 2; ++k) {
+        s.rec_a[k] = (int32_t *)(b + L.rec[k][0]);
+        s.rec_b[k] = (int32_t *)(b + L.rec[k][1]);
+        s.rec_c[k] = (int32_t *)(b + L.rec[k][2]);
+        s.rec_vb[k] = (int32_t *)(b + L.rec[k][3]);
+        s.rec_key[k] = (uint64_t *)(b + L.rec[k][4]);
+    }
     s.stats = (RoundStats *)(b + L.stats);
     s.ring = L.ring;
     s.grid = L.grid;
@@ -438,7 +452,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                                                                                     : kClearPins;
             HGM_TRY(launch_test(L, g, s, r, clear, matched_bits, kseed(r)));
             HGM_TRY(T.after(HGM_K_TEST, r));
-            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1)));
+            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1), o.reseed ? 1 : 0));
             HGM_TRY(T.after(HGM_K_RETIRE, r));
             if (next_crew) {
                 HGM_TRY(launch_vertex_max(L, g, s, r + 1, seed));

@@ -103,6 +103,14 @@ struct State {
     uint8_t *done;      // [n] vertex is a pin of a matched edge
     int32_t *list[2];   // [grid * region] live edges per workgroup region
     int32_t *cnt[2];    // [grid] live edges per region
+    // Edge records beside list[] (same index), written by the retire pass for
+    // every survivor so that the next kernels read them with the id instead
+    // of gathering through it.  Offset layout: rec_a = first pin offset,
+    // rec_b = pin count, rec_c = first pin (vertex id, batch base added).
+    // Pair layout: rec_a, rec_b = the two pins.  rec_key = the key of the
+    // list's round; rec_vb = the edge's vertex base (batch only).
+    int32_t *rec_a[2], *rec_b[2], *rec_c[2], *rec_vb[2];
+    uint64_t *rec_key[2];
     RoundStats *stats;  // [ring]
     int32_t ring;
     int32_t grid;       // edge-kernel workgroups
@@ -132,14 +140,15 @@ struct Launch {
 constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
 constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
 // `kseed` arguments: the priority seed of the round the kernel works on
-// (the call's seed, or round_seed(seed, r) when the order is redrawn).
+// (the call's seed, or round_seed(seed, r) when the order is redrawn);
+// `rekey`: nonzero when the order is redrawn every round.
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
                        uint32_t *bits, int init_flags);
 hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed);
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
-                         uint32_t kseed);
+                         uint32_t kseed, int rekey);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
                              uint32_t seed);
 // Round-0 maximum in the form chosen from the degree profile (AUTO): two

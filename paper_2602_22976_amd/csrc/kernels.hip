@@ -360,6 +360,60 @@ __device__ __forceinline__ int region_item(const State &s, int round, int b, int
     return round == 0 ? (int)at : s.list[round & 1][at];
 }
 
+// Edge i of workgroup b's live list of round r, offset layout: id, pin offset
+// and count, first pin (-1 if none), vertex base and key.  Round 0's list is
+// the identity and reads the hypergraph.  Later lists read the records that
+// the retire pass wrote beside the ids, at the same index, so one step
+// replaces the gathers through the id.  rekey: the caller's round orders by a
+// different seed than the list's round (per-round priorities), so the key is
+// rebuilt from the weight.
+struct EdgeRec {
+    int e, base, len, pin0, vb;
+    uint64_t key;
+};
+
+template <bool kB>
+__device__ __forceinline__ EdgeRec edge_rec(const Graph &g, const State &s, int round, int b,
+                                            int i, uint32_t kseed, bool rekey) {
+    EdgeRec r;
+    const int64_t at = (int64_t)b * s.region + i;
+    if (round == 0) {
+        r.e = (int)at;
+        r.base = g.e_off[r.e];
+        r.len = g.e_off[r.e + 1] - r.base;
+        r.vb = kB ? g.vbase[r.e] : 0;
+        r.key = edge_key<kB>(g, s, kseed, r.e);
+        r.pin0 = r.len > 0 ? g.e_pins[r.base] + r.vb : -1;
+    } else {
+        const int k = round & 1;
+        r.e = s.list[k][at];
+        r.base = s.rec_a[k][at];
+        r.len = s.rec_b[k][at];
+        r.pin0 = s.rec_c[k][at];
+        r.vb = kB ? s.rec_vb[k][at] : 0;
+        r.key = rekey ? edge_key<kB>(g, s, kseed, r.e) : s.rec_key[k][at];
+    }
+    return r;
+}
+
+// The same for the pair layout: id, both pins, key.
+template <bool kB>
+__device__ __forceinline__ void pair_rec(const Graph &g, const State &s, int round, int b, int i,
+                                         uint32_t kseed, bool rekey, int &e, int2 &p,
+                                         uint64_t &key) {
+    const int64_t at = (int64_t)b * s.region + i;
+    if (round == 0) {
+        e = (int)at;
+        p = pair_pins(g, e);
+        key = edge_key<kB>(g, s, kseed, e);
+    } else {
+        const int k = round & 1;
+        e = s.list[k][at];
+        p = make_int2(s.rec_a[k][at], s.rec_b[k][at]);
+        key = rekey ? edge_key<kB>(g, s, kseed, e) : s.rec_key[k][at];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Edge-centric scatter of round 0 (Algorithm 1, per-vertex maximum by
 // concurrent writes): every edge raises best[pin] to its key at each pin.
@@ -425,8 +479,12 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 // pins is done; this removes the edges matched in round r-1 (all their pins
 // are done) and every edge that touches them (Algorithm 2's OR-reduction over
 // the pins of each edge).  Survivors are compacted, in order, into the
-// workgroup's region of list[r & 1]; the count goes to cnt[r & 1][b] and the
-// round's counters.  Then, depending on the variant:
+// workgroup's region of list[r & 1], each with its record (pin offset and
+// count or the two pins, first pin, vertex base, round-r key) at the same
+// index; the count goes to cnt[r & 1][b] and the round's counters.  rekey:
+// round r orders by a different seed than round r-1, so keys are rebuilt
+// from the weights instead of read from the input records.  Then, depending
+// on the variant:
 //   scatter = 1 (CRCW): each survivor raises best[r & 1][pin] at its pins.
 //   scatter = 0 (CREW): non-survivors get live_key = 0, and the split hub
 //                       vertices' best[r & 1] and vlen[r & 1] are cleared for
@@ -435,12 +493,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 // combination is its own kernel: a kernel holding every path runs the hot
 // one slower.
 template <bool kPairs, bool kScatter, bool kB>
-__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed) {
+__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed,
+                                                   int rekey) {
     constexpr bool scatter = kScatter;
     __shared__ ChunkLds L;
     const int b = blockIdx.x;
     const int cnt = region_count(s, g.m, round - 1, b);
-    int32_t *out_list = s.list[round & 1] + (int64_t)b * s.region;
+    const int64_t out0 = (int64_t)b * s.region;  // the region's first list slot
+    int32_t *out_list = s.list[round & 1] + out0;
+    const int ko = round & 1;                     // records of the list written here
     uint64_t *best = s.best[round & 1];
     RoundStats *st_out = &s.stats[round % s.ring];
 
@@ -461,17 +522,21 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             const int i = c0 + threadIdx.x;
             int e = -1, alive = 0;
             int2 p = make_int2(0, 0);
+            uint64_t key = 0;
             if (i < cnt) {
-                e = region_item(s, round - 1, b, i);
-                p = pair_pins(g, e);
+                pair_rec<kB>(g, s, round - 1, b, i, kseed, rekey != 0, e, p, key);
                 alive = (s.done[p.x] | s.done[p.y]) ? 0 : 1;
             }
             if (!scatter && e >= 0 && !alive) s.live_key[e] = 0;
             int n_alive;
             const int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
             if (alive) {
+                const int64_t at = out0 + out_pos + pos;
                 out_list[out_pos + pos] = e;
-                if (scatter) scatter_pair(best, p, edge_key<kB>(g, s, kseed, e));
+                s.rec_a[ko][at] = p.x;
+                s.rec_b[ko][at] = p.y;
+                s.rec_key[ko][at] = key;
+                if (scatter) scatter_pair(best, p, key);
             }
             out_pos += n_alive;
         }
@@ -479,15 +544,17 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
     }
     for (int c0 = 0; c0 < cnt && !kPairs; c0 += kBlock) {
         const int i = c0 + threadIdx.x;
-        int e = -1, len = 0, base = 0;
+        int e = -1, len = 0, base = 0, pin0 = -1;
         uint64_t key = 0;
         int vb = 0;
         if (i < cnt) {
-            e = region_item(s, round - 1, b, i);
-            base = g.e_off[e];
-            len = g.e_off[e + 1] - base;
-            key = edge_key<kB>(g, s, kseed, e);
-            if constexpr (kB) vb = g.vbase[e];
+            const EdgeRec r = edge_rec<kB>(g, s, round - 1, b, i, kseed, rekey != 0);
+            e = r.e;
+            base = r.base;
+            len = r.len;
+            pin0 = r.pin0;
+            key = r.key;
+            vb = r.vb;
         }
         // The first kUnroll pins one lane per edge: most retired edges are
         // found there, and most edges have no more pins.  The pins beyond
@@ -497,8 +564,9 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         bool dead = false;
         {
             int p[kUnroll];
+            p[0] = len > 0 ? pin0 : -1;
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) p[u] = u < len ? g.e_pins[base + u] + vb : -1;
+            for (int u = 1; u < kUnroll; ++u) p[u] = u < len ? g.e_pins[base + u] + vb : -1;
             uint8_t dv[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) dv[u] = p[u] >= 0 ? s.done[p[u]] : 0;
@@ -537,7 +605,15 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         if (!scatter && e >= 0 && !alive) s.live_key[e] = 0;
         int n_alive;
         int pos = block_exclusive_sum(alive, L.wave_tmp, &n_alive);
-        if (alive) out_list[out_pos + pos] = e;
+        if (alive) {
+            const int64_t at = out0 + out_pos + pos;
+            out_list[out_pos + pos] = e;
+            s.rec_a[ko][at] = base;
+            s.rec_b[ko][at] = len;
+            s.rec_c[ko][at] = pin0;
+            if constexpr (kB) s.rec_vb[ko][at] = vb;
+            s.rec_key[ko][at] = key;
+        }
         out_pos += n_alive;
         int total2;
         int st2 = block_exclusive_sum(alive ? len : 0, L.wave_tmp, &total2);
@@ -782,9 +858,10 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
     unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
     if constexpr (kPairs) {
         for (int i = threadIdx.x; i < cnt; i += kBlock) {
-            const int e = region_item(s, round, b, i);
-            const int2 p = pair_pins(g, e);
-            const uint64_t key = edge_key<kB>(g, s, kseed, e);
+            int e;
+            int2 p;
+            uint64_t key;
+            pair_rec<kB>(g, s, round, b, i, kseed, false, e, p, key);
             const uint64_t b0 = best[p.x], b1 = best[p.y];
             if constexpr (clear_pins) {
                 next[p.x] = 0;
@@ -817,28 +894,29 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         // takes kTestEdges edges per step with their loads issued together,
         // so their dependent chains (id, offsets, pin, maximum) overlap.
         for (int c0 = 0; c0 < cnt; c0 += kTestEdges * kBlock) {
-            int e[kTestEdges], len[kTestEdges], base[kTestEdges], vb[kTestEdges];
+            int e[kTestEdges], len[kTestEdges], base[kTestEdges], vb[kTestEdges], pin0[kTestEdges];
             uint64_t key[kTestEdges];
             bool ok[kTestEdges];
 #pragma unroll
             for (int u = 0; u < kTestEdges; ++u) {
                 const int i = c0 + u * kBlock + threadIdx.x;
-                e[u] = i < cnt ? region_item(s, round, b, i) : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < kTestEdges; ++u) {
+                e[u] = -1;
                 len[u] = base[u] = vb[u] = 0;
+                pin0[u] = -1;
                 key[u] = 0;
-                if (e[u] >= 0) {
-                    base[u] = g.e_off[e[u]];
-                    len[u] = g.e_off[e[u] + 1] - base[u];
-                    key[u] = edge_key<kB>(g, s, kseed, e[u]);
-                    if constexpr (kB) vb[u] = g.vbase[e[u]];
+                if (i < cnt) {
+                    const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false);
+                    e[u] = r.e;
+                    base[u] = r.base;
+                    len[u] = r.len;
+                    pin0[u] = r.pin0;
+                    key[u] = r.key;
+                    vb[u] = r.vb;
                 }
             }
 #pragma unroll
             for (int u = 0; u < kTestEdges; ++u)
-                ok[u] = e[u] >= 0 && (len[u] == 0 || best[g.e_pins[base[u]] + vb[u]] == key[u]);
+                ok[u] = e[u] >= 0 && (len[u] == 0 || best[pin0[u]] == key[u]);
 #pragma unroll
             for (int u = 0; u < kTestEdges; ++u) {
                 // the rest of the pins, kUnroll at a time, while still the maximum
@@ -865,11 +943,12 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         uint64_t key = 0;
         int vb = 0;
         if (i < cnt) {
-            e = region_item(s, round, b, i);
-            base = g.e_off[e];
-            len = g.e_off[e + 1] - base;
-            key = edge_key<kB>(g, s, kseed, e);
-            if constexpr (kB) vb = g.vbase[e];
+            const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false);
+            e = r.e;
+            base = r.base;
+            len = r.len;
+            key = r.key;
+            vb = r.vb;
         }
         int total;
         int st = block_exclusive_sum(len, L.wave_tmp, &total);
@@ -1021,10 +1100,10 @@ hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint3
 }
 
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
-                         uint32_t kseed) {
+                         uint32_t kseed, int rekey) {
     const dim3 grid(s.grid), block(kBlock);
 #define HGM_RETIRE(P, S, B) \
-    hipLaunchKernelGGL((k_retire<P, S, B>), grid, block, 0, L.stream, g, s, round, kseed)
+    hipLaunchKernelGGL((k_retire<P, S, B>), grid, block, 0, L.stream, g, s, round, kseed, rekey)
     if (g.pairs) {
         if (scatter) HGM_RETIRE(true, true, false);
         else HGM_RETIRE(true, false, false);

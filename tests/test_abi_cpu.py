@@ -56,10 +56,11 @@ def test_workspace_size_layout(lib):
     small = hgm.hgm_workspace_size(_csr(10, 20, 100))
     big = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000))
     assert 0 < small < big
-    # two max buffers 16n, done n, two lists 8m at least (keys are rebuilt
-    # from the weights for one instance, not stored)
-    assert big >= 8 * 5_000_000 + 17 * 2_000_000
-    assert big < 8 * 5_000_000 + 17 * 2_000_000 + 8 * 5_000_000
+    # two max buffers 16n, done n, two lists with their edge records (id 4,
+    # pin offset 4, pin count 4, first pin 4, key 8) 48m at least; keys are
+    # not stored per edge for one instance
+    assert big >= 48 * 5_000_000 + 17 * 2_000_000
+    assert big < 48 * 5_000_000 + 17 * 2_000_000 + 8 * 5_000_000
     rs = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts(reseed=True))
     assert rs == big
     crew = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts("crew"))
