@@ -854,6 +854,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         const int64_t stride = (int64_t)gridDim.x * kBlock;
         for (int64_t v = (int64_t)b * kBlock + threadIdx.x; v < g.n; v += stride) next[v] = 0;
     }
+    if (cnt == 0) return;  // an empty region (most of them in late rounds): no counters
     constexpr bool clear_pins = kClear == kClearPins;
     unsigned long long nm = 0, wm = 0, pm = 0;  // per-thread partial counters
     if constexpr (kPairs) {
