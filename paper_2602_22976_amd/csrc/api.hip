@@ -35,7 +35,7 @@ struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
     size_t key, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
-        piece_count, hot, vbits, goff, vbase, bitoff, gvoff, ebase, total;
+        piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
 };
 
@@ -138,6 +138,7 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     L.pieces = take(sizeof(int2) * (size_t)L.piece_cap);
     L.piece_count = take(4);
     L.hot = take(8 * (size_t)kSub);
+    L.wrange = take(8 * (size_t)kSub);
     L.vbits = take(o.validate ? 4 * (size_t)((kappa + 31) / 32) : 0);
     // Batch: global offsets and per-edge / per-vertex bases (see Graph).
     L.goff = take(batch ? 4 * ((size_t)m + 1) : 0);
@@ -181,6 +182,7 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.pieces = (int2 *)(b + L.pieces);
     s.piece_count = (int32_t *)(b + L.piece_count);
     s.hot = (unsigned long long *)(b + L.hot);
+    s.wrange = (uint32_t *)(b + L.wrange);
     s.piece_cap = L.piece_cap;
     s.hub_threshold = o.hub_threshold;
     s.vbits = (uint32_t *)(b + L.vbits);
@@ -374,6 +376,9 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     // Priority seed of round r.
     auto kseed = [&](int r) { return o.reseed ? round_seed(seed, r) : seed; };
     if (any_crew_round(o)) init_flags |= kInitHubs;
+    // Round 0's vertex pass of one instance skips the weight gathers when all
+    // weights are equal (cardinality matching); batches gather stored keys.
+    if (crew_round(o, 0) && !batch) init_flags |= kInitWeightRange;
     KernelTimer T;
     T.on = stats && stats->timing;
     T.stream = L.stream;

@@ -258,15 +258,21 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
         *s.err = 0;
         *s.piece_count = 0;
     }
-    if (threadIdx.x < kSub) s.hot[threadIdx.x] = 0;
+    if (threadIdx.x < kSub) {
+        s.hot[threadIdx.x] = 0;
+        s.wrange[2 * threadIdx.x] = 0xFFFFFFFFu;
+        s.wrange[2 * threadIdx.x + 1] = 0;
+    }
 }
 
-// Setup: cleared per-vertex state and bitmap; optionally the CREW live keys
-// and the pieces of high-degree vertices.
+// Setup: cleared per-vertex state and bitmap; optionally the CREW live keys,
+// the pieces of high-degree vertices and the weight range.
 __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s, uint32_t *bits,
                                                  int flags) {
     __shared__ unsigned long long sum_tmp[kWaves];
+    __shared__ uint32_t wlo, whi;
     unsigned long long hot = 0;
+    uint32_t wmin = 0xFFFFFFFFu, wmax = 0;
     const int64_t words = g.words;
     const int64_t edges = (flags & kInitLiveKey) ? g.m : 0;  // edge-indexed work: live keys only
     const int64_t span = edges > g.n ? edges : g.n;
@@ -295,6 +301,36 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     if (flags & kInitHubs) {
         hot = block_sum_u64(hot, sum_tmp);
         if (threadIdx.x == 0 && hot) atomicAdd(&s.hot[blockIdx.x % kSub], hot);
+    }
+    if (flags & kInitWeightRange) {
+        // Four independent loads per step: a loop that consumes each load
+        // before issuing the next waits one memory latency per step.
+        int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        for (; i + 3 * stride < g.m; i += 4 * stride) {
+            const uint32_t a = g.w[i], b = g.w[i + stride], c = g.w[i + 2 * stride],
+                           d = g.w[i + 3 * stride];
+            const uint32_t lo = min(min(a, b), min(c, d)), hi = max(max(a, b), max(c, d));
+            wmin = lo < wmin ? lo : wmin;
+            wmax = hi > wmax ? hi : wmax;
+        }
+        for (; i < g.m; i += stride) {
+            const uint32_t wi = g.w[i];
+            wmin = wi < wmin ? wi : wmin;
+            wmax = wi > wmax ? wi : wmax;
+        }
+        if (threadIdx.x == 0) {
+            wlo = 0xFFFFFFFFu;
+            whi = 0;
+        }
+        __syncthreads();
+        atomicMin(&wlo, wmin);
+        atomicMax(&whi, wmax);
+        __syncthreads();
+        if (threadIdx.x == 0 && whi >= wlo) {  // spread over kSub slots: atomics on one
+            const int k = blockIdx.x % kSub;     // address serialise
+            atomicMin(&s.wrange[2 * k], wlo);
+            atomicMax(&s.wrange[2 * k + 1], whi);
+        }
     }
 }
 
@@ -656,9 +692,37 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
 // whole list.  Round 1 reads the caller's lists.  Non-hub positions come from
 // an LDS counter per vertex; a hub's from one global atomic per wave on its
 // vlen entry (cleared by the retire pass).
+// The weight range k_init left in kSub slots: smallest weight, and whether
+// every weight equals it (false when there are no edges).
+__device__ __forceinline__ void weight_range(const State &s, uint32_t *wlo, bool *uniform) {
+    __shared__ uint32_t lo, hi;
+    if (threadIdx.x < kWave) {
+        uint32_t a = threadIdx.x < kSub ? s.wrange[2 * threadIdx.x] : 0xFFFFFFFFu;
+        uint32_t c = threadIdx.x < kSub ? s.wrange[2 * threadIdx.x + 1] : 0;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            const uint32_t a2 = __shfl_xor(a, o, kWave), c2 = __shfl_xor(c, o, kWave);
+            a = a2 < a ? a2 : a;
+            c = c2 > c ? c2 : c;
+        }
+        if (threadIdx.x == 0) {
+            lo = a;
+            hi = c;
+        }
+    }
+    __syncthreads();
+    *wlo = lo;
+    *uniform = lo == hi;
+}
+
+// uniform_w: every weight equals wlo (one instance, round 0), so the key
+// needs no gather.
 template <bool kB>
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
-                                               uint32_t seed, int e) {
+                                               uint32_t seed, int e, bool uniform_w,
+                                               uint32_t wlo) {
+    if (!kB && round == 0 && uniform_w)
+        return ((uint64_t)wlo << 32) | priority_hash(seed, (uint32_t)e);
     return round == 0 ? edge_key<kB>(g, s, seed, e) : s.live_key[e];
 }
 
@@ -669,6 +733,11 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
     uint64_t *best = s.best[round & 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int hub_threshold = s.hub_threshold;
+    // Round 0 of one instance: k_init left the weight range (all equal:
+    // keys without a gather).  Other rounds gather stored keys.
+    uint32_t wlo = 0;
+    bool uniform_w = false;
+    if (!kB && round == 0) weight_range(s, &wlo, &uniform_w);
     constexpr bool compact = kCompact;
     // Lists read this round: the caller's (local ids in a batch, full degree)
     // up to round 1, then the ones compacted by the previous round.
@@ -696,7 +765,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             uint64_t k = 0;
             if (i < p1) {
                 e = src[vo + i] + eb;
-                k = vertex_key<kB>(g, s, round, seed, e);
+                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo);
             }
             mx = k > mx ? k : mx;
             if constexpr (compact) {
@@ -742,7 +811,7 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             if (t < total) {
                 j = find_item(L.start, t);
                 const int e = src[L.base[j] + (t - L.start[j])] + (kB ? L.vb[j] : 0);
-                k = vertex_key<kB>(g, s, round, seed, e);
+                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo);
                 if constexpr (compact) {
                     if (k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
                 }

@@ -146,6 +146,24 @@ def test_edge_with_key_zero(hgm, variant):
     assert oracle.bits_to_bool(got, 3).tolist() == [True, True, True]
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("wval", [0, 1, 12345, 0xFFFFFFFF])
+def test_uniform_weights(hgm, variant, wval):
+    """All weights equal (cardinality matching): round 0's vertex pass builds
+    keys without gathering the weights.  The same instance with one weight
+    changed must take the gathering path and follow it (the changed edge is
+    the heaviest, so it is matched)."""
+    g = synth.random_instance(123, 3000, 8000, 2, 9, 1, 1)
+    g.w[:] = wval
+    print(f"uniform weights w={wval} variant={variant}", flush=True)
+    _check(hgm, g, 5, variant)
+    if wval < 0xFFFFFFFF:
+        g.w[4321] = wval + 1
+        bits, _, _, _ = _expect(g, 5)
+        assert oracle.bits_to_bool(bits, g.m)[4321]
+        _check(hgm, g, 5, variant)
+
+
 @pytest.mark.parametrize("threshold", [1, 4, 64, 100_000])
 def test_crew_hub_split(hgm, threshold):
     g = synth.config_hub_stress(seed=21, n=5000, m=40_000)
