@@ -378,7 +378,9 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     if (any_crew_round(o)) init_flags |= kInitHubs;
     // Round 0's vertex pass of one instance skips the weight gathers when all
     // weights are equal (cardinality matching); batches gather stored keys.
-    if (crew_round(o, 0) && !batch) init_flags |= kInitWeightRange;
+    // CREW: setup finds the weight range.  AUTO: the round-0 edge kernel does,
+    // only when it leaves the round to the vertex form.
+    if (o.variant == HGM_VARIANT_CREW && !batch) init_flags |= kInitWeightRange;
     KernelTimer T;
     T.on = stats && stats->timing;
     T.stream = L.stream;

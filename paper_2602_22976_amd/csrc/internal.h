@@ -122,7 +122,8 @@ struct State {
                         // vertex of degree > hub threshold is cut into kHubPiece pieces
     int32_t *piece_count;  // [1]
     unsigned long long *hot;  // [kSub] incidences on vertices of degree >= kHotDegree
-    uint32_t *wrange;   // [2 * kSub] smallest and largest weight (kInitWeightRange): slot
+    uint32_t *wrange;   // [2 * kSub] smallest and largest weight (kInitWeightRange, or
+                        // AUTO's round-0 edge kernel when the vertex form runs): slot
                         // k holds workgroups b = k mod kSub, min at 2k, max at 2k + 1
     int32_t *vedges[2]; // [kappa] live incident edges of each vertex (global ids) at the
                         // front of its v_off segment, compacted by the vertex pass of
@@ -141,8 +142,8 @@ struct Launch {
 // init_flags: which optional setup k_init performs.
 constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
 constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
-constexpr int kInitWeightRange = 4;  // smallest and largest weight (round-0 vertex pass, one
-                                     // instance: equal weights need no gather)
+constexpr int kInitWeightRange = 4;  // smallest and largest weight (CREW round-0 vertex pass,
+                                     // one instance: equal weights need no gather)
 // `kseed` arguments: the priority seed of the round the kernel works on
 // (the call's seed, or round_seed(seed, r) when the order is redrawn);
 // `rekey`: nonzero when the order is redrawn every round.

@@ -265,14 +265,48 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
     }
 }
 
+// Smallest and largest weight into wrange's kSub slots (the whole grid
+// takes part; slot k collects workgroups b = k mod kSub).
+__device__ void reduce_weight_range(const Graph &g, const State &s) {
+    __shared__ uint32_t wlo, whi;
+    uint32_t wmin = 0xFFFFFFFFu, wmax = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // Four independent loads per step: a loop that consumes each load
+    // before issuing the next waits one memory latency per step.
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < g.m; i += 4 * stride) {
+        const uint32_t a = g.w[i], b = g.w[i + stride], c = g.w[i + 2 * stride],
+                       d = g.w[i + 3 * stride];
+        const uint32_t lo = min(min(a, b), min(c, d)), hi = max(max(a, b), max(c, d));
+        wmin = lo < wmin ? lo : wmin;
+        wmax = hi > wmax ? hi : wmax;
+    }
+    for (; i < g.m; i += stride) {
+        const uint32_t wi = g.w[i];
+        wmin = wi < wmin ? wi : wmin;
+        wmax = wi > wmax ? wi : wmax;
+    }
+    if (threadIdx.x == 0) {
+        wlo = 0xFFFFFFFFu;
+        whi = 0;
+    }
+    __syncthreads();
+    atomicMin(&wlo, wmin);
+    atomicMax(&whi, wmax);
+    __syncthreads();
+    if (threadIdx.x == 0 && whi >= wlo) {  // spread over kSub slots: atomics on one
+        const int k = blockIdx.x % kSub;     // address serialise
+        atomicMin(&s.wrange[2 * k], wlo);
+        atomicMax(&s.wrange[2 * k + 1], whi);
+    }
+}
+
 // Setup: cleared per-vertex state and bitmap; optionally the CREW live keys,
 // the pieces of high-degree vertices and the weight range.
 __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s, uint32_t *bits,
                                                  int flags) {
     __shared__ unsigned long long sum_tmp[kWaves];
-    __shared__ uint32_t wlo, whi;
     unsigned long long hot = 0;
-    uint32_t wmin = 0xFFFFFFFFu, wmax = 0;
     const int64_t words = g.words;
     const int64_t edges = (flags & kInitLiveKey) ? g.m : 0;  // edge-indexed work: live keys only
     const int64_t span = edges > g.n ? edges : g.n;
@@ -302,36 +336,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
         hot = block_sum_u64(hot, sum_tmp);
         if (threadIdx.x == 0 && hot) atomicAdd(&s.hot[blockIdx.x % kSub], hot);
     }
-    if (flags & kInitWeightRange) {
-        // Four independent loads per step: a loop that consumes each load
-        // before issuing the next waits one memory latency per step.
-        int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        for (; i + 3 * stride < g.m; i += 4 * stride) {
-            const uint32_t a = g.w[i], b = g.w[i + stride], c = g.w[i + 2 * stride],
-                           d = g.w[i + 3 * stride];
-            const uint32_t lo = min(min(a, b), min(c, d)), hi = max(max(a, b), max(c, d));
-            wmin = lo < wmin ? lo : wmin;
-            wmax = hi > wmax ? hi : wmax;
-        }
-        for (; i < g.m; i += stride) {
-            const uint32_t wi = g.w[i];
-            wmin = wi < wmin ? wi : wmin;
-            wmax = wi > wmax ? wi : wmax;
-        }
-        if (threadIdx.x == 0) {
-            wlo = 0xFFFFFFFFu;
-            whi = 0;
-        }
-        __syncthreads();
-        atomicMin(&wlo, wmin);
-        atomicMax(&whi, wmax);
-        __syncthreads();
-        if (threadIdx.x == 0 && whi >= wlo) {  // spread over kSub slots: atomics on one
-            const int k = blockIdx.x % kSub;     // address serialise
-            atomicMin(&s.wrange[2 * k], wlo);
-            atomicMax(&s.wrange[2 * k + 1], whi);
-        }
-    }
+    if (flags & kInitWeightRange) reduce_weight_range(g, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -875,7 +880,12 @@ __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t
     __shared__ HubTable H;
     const bool edge_form = max0_edge_form(g, s);
     if (blockIdx.x == 0 && threadIdx.x == 0) s.stats[0].form = edge_form ? 1 : 2;
-    if (!edge_form) return;
+    if (!edge_form) {
+        // The vertex form follows: its keys need no weight gather when all
+        // weights are equal (one instance), which the range shows.
+        if constexpr (!kB) reduce_weight_range(g, s);
+        return;
+    }
     hub_table_build(H, s);
     scatter0_region<kPairs, kB>(g, s, L, blockIdx.x, seed, &H);
 }
