@@ -6,7 +6,7 @@ mathematics, independent of the oracle's own code.
 * Greedy: the greedy certificate (matching + every rejected edge blocked by a
   higher matched neighbour), which characterises the greedy set uniquely;
   Lemma 1's 1/d bound against brute-force optima; Lemma 2's tight instance.
-* Local max: equals greedy for a strict order (the induction in the design doc),
+* Local max: equals greedy for a strict order (induction down the key order),
   closed forms on paths, stars and disjoint edges, statistics invariants.
 * Planted mistakes in a result are caught by the certificate.
 """
