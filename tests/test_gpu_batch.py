@@ -119,3 +119,48 @@ def test_batch_workload_sample(hgm):
     per, rounds = _oracle_batch(b)
     for variant in ("auto", "crcw"):
         _check_batch(hgm, b, variant, per, rounds)
+
+
+def test_batch_full_workload(hgm):
+    """The full batched workload that bench.py times (4,096 instances, sum of
+    kappa about 4.8e8, one launch): a seeded sample of instances, with the
+    largest and the smallest, equals the oracle bit for bit; every instance's
+    segment is a maximal matching, checked over the whole concatenation with
+    instance-global vertex ids; the totals add up."""
+    import torch
+    b = synth.config_batched(seed=1004, count=4096)
+    kap = np.diff(b.pin_base)
+    print(f"full batched workload: m_total={int(b.e_base[-1])} kappa_total={int(kap.sum())}",
+          flush=True)
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    bits, st = hgm.match_batch(db, hgm.make_opts("auto"))
+    torch.cuda.synchronize()
+    got = bits.cpu().numpy().view(np.uint32)
+    del db, bits
+    torch.cuda.empty_cache()
+    segs = _segments(b, got)
+
+    rng = np.random.Generator(np.random.PCG64(4096))
+    sample = set(rng.choice(b.count, 10, replace=False).tolist())
+    sample |= {int(np.argmax(kap)), int(np.argmin(kap))}
+    for i in sorted(sample):
+        g = b.instance(i)
+        exp = oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, int(b.seeds[i]))[0]
+        assert np.array_equal(segs[i], exp), f"instance {i} differs"
+
+    matched = np.concatenate([oracle.bits_to_bool(segs[i], int(b.m[i])) for i in range(b.count)])
+    sizes = np.concatenate([np.diff(b.e_off[b.e_base[i] + i: b.e_base[i + 1] + i + 1])
+                            for i in range(b.count)])
+    assert sizes.min() > 0   # |e| >= 2 in this workload (reduceat below needs non-empty edges)
+    gp = b.e_pins + np.repeat(b.v_base[:-1].astype(np.int32), kap)   # instance-global vertex ids
+    mp = gp[np.repeat(matched, sizes)]
+    n_total = int(b.v_base[-1])
+    assert np.bincount(mp, minlength=n_total).max() <= 1              # vertex-disjoint
+    covered = np.zeros(n_total, dtype=bool)
+    covered[mp] = True
+    starts = np.zeros(sizes.size, dtype=np.int64)
+    np.cumsum(sizes[:-1], out=starts[1:])
+    hit = np.logical_or.reduceat(covered[gp], starts)
+    assert np.all(matched | hit)                                      # maximal
+    assert st["matched"] == int(matched.sum())
+    assert st["weight"] == int(b.w[matched].astype(np.uint64).sum())
