@@ -96,6 +96,35 @@ def test_degenerate_batches(hgm, variant):
     _check_batch(hgm, one, variant)
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_skewed_batch(hgm, variant):
+    """One large instance among thousands of tiny and empty ones, in three
+    orders (large first, in the middle, last): the setup's workgroups each
+    take an equal range of edges and of vertices, so one range spans dozens
+    of tiny instances and the empty ones between them, while many ranges
+    fall inside the large one; every instance's segment must still equal the
+    oracle."""
+    rng = np.random.default_rng(11)
+    big = synth.random_instance(21, 60_000, 150_000, 2, 12, 1, 1000)
+    tiny = []
+    for k in range(3000):
+        kind = k % 5
+        if kind == 0:
+            tiny.append(synth.from_edge_lists(0, [], []))                       # nothing
+        elif kind == 1:
+            tiny.append(synth.from_edge_lists(int(rng.integers(1, 4)), [], []))  # vertices only
+        else:
+            n = int(rng.integers(2, 9))
+            tiny.append(synth.random_instance(1000 + k, n, int(rng.integers(1, 6)), 1, min(3, n),
+                                              0, 5))
+    for at in (0, 1500, 3000):
+        gs = tiny[:at] + [big] + tiny[at:]
+        seeds = rng.integers(0, 2 ** 32, size=len(gs)).astype(np.uint32)
+        b = synth.batch_from_instances(gs, seeds)
+        print(f"skewed batch: large instance at {at}, variant={variant}", flush=True)
+        _check_batch(hgm, b, variant)
+
+
 def test_batch_equals_single_calls(hgm):
     import torch
     b = synth.config_batched(seed=5, count=40, n_lo=100, n_hi=5000)
