@@ -87,6 +87,33 @@ def test_graph_degenerate(hgm, variant):
         _check(hgm, g, 1, variant)
 
 
+@pytest.mark.parametrize("weights", ["equal", "random"])
+def test_hub_heavy_graphs_take_the_edge_form(hgm, weights):
+    """Graphs whose incidences sit mostly on high-degree vertices, so AUTO
+    takes the edge-centric round 0 in the pair layout: a star (every edge
+    meets the centre: one match), two stars joined by an edge between their
+    centres, and the complete bipartite graph K(80, 80) (every vertex of
+    degree 80; several rounds)."""
+    rng = np.random.default_rng(17)
+    k = 3000
+    star = np.stack([np.zeros(k, dtype=np.int64), np.arange(1, k + 1)], 1)
+    two = np.concatenate([star, np.stack([np.full(k, k + 1), np.arange(k + 2, 2 * k + 2)], 1),
+                          [[0, k + 1]]])
+    a, c = np.meshgrid(np.arange(80), np.arange(80, 160), indexing="ij")
+    kbip = np.stack([a.reshape(-1), c.reshape(-1)], 1)
+    for name, pairs, n in (("star", star, k + 1), ("two stars", two, 2 * k + 2),
+                           ("K(80,80)", kbip, 160)):
+        m = len(pairs)
+        w = np.ones(m, dtype=np.int64) if weights == "equal" else rng.integers(1, 1000, m)
+        g = synth.from_pairs(n, pairs, w)
+        deg = np.diff(g.v_off)
+        assert 2 * int(deg[deg >= 64].sum()) >= g.kappa   # AUTO's edge-form condition
+        print(f"hub-heavy graph {name} m={m} weights={weights}", flush=True)
+        st = _check(hgm, g, 3, "auto")
+        if name == "star":
+            assert st["matched"] == 1 and st["rounds"] == 1
+
+
 def test_path_graph_pairs_rounds(hgm):
     """Increasing weights along a path: ceil(m / 2) rounds, one match every
     two rounds from the heavy end; with the pair layout too."""
