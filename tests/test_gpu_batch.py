@@ -52,12 +52,12 @@ def _agg(rounds, key):
     return tot
 
 
-def _check_batch(hgm, b, variant, per=None, rounds=None):
+def _check_batch(hgm, b, variant, per=None, rounds=None, **kw):
     import torch
     if per is None:
         per, rounds = _oracle_batch(b)
     db = hgm.DeviceBatch.from_host(b, "cuda:0")
-    bits, st = hgm.match_batch(db, hgm.make_opts(variant))
+    bits, st = hgm.match_batch(db, hgm.make_opts(variant, **kw))
     torch.cuda.synchronize()
     got = bits.cpu().numpy().view(np.uint32)
     segs = _segments(b, got)
@@ -123,6 +123,25 @@ def test_skewed_batch(hgm, variant):
         b = synth.batch_from_instances(gs, seeds)
         print(f"skewed batch: large instance at {at}, variant={variant}", flush=True)
         _check_batch(hgm, b, variant)
+
+
+@pytest.mark.parametrize("threshold", [0, 64, 300])
+def test_dense_batch_takes_the_edge_form(hgm, threshold):
+    """Dense instances (every vertex of degree about 100), so AUTO's round 0
+    takes the edge-centric form over the batch; with a low hub threshold the
+    high-degree vertices become hubs reduced in each workgroup's table."""
+    rng = np.random.default_rng(23)
+    gs = []
+    for k in range(24):
+        n = int(rng.integers(60, 140))
+        gs.append(synth.random_instance(500 + k, n, 2000, 2, 8, 1, int(rng.integers(1, 1000))))
+    gs.append(synth.random_instance(600, 3000, 500, 2, 4, 1, 9))   # a sparse one among them
+    seeds = rng.integers(0, 2 ** 32, size=len(gs)).astype(np.uint32)
+    b = synth.batch_from_instances(gs, seeds)
+    deg = np.concatenate([np.diff(b.instance(i).v_off) for i in range(b.count)])
+    assert 2 * int(deg[deg >= 64].sum()) >= int(b.pin_base[-1])   # AUTO's edge-form condition
+    print(f"dense batch hub_threshold={threshold}", flush=True)
+    _check_batch(hgm, b, "auto", hub_threshold=threshold)
 
 
 def test_batch_equals_single_calls(hgm):
