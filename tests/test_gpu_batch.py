@@ -125,11 +125,13 @@ def test_skewed_batch(hgm, variant):
         _check_batch(hgm, b, variant)
 
 
+@pytest.mark.parametrize("variant", ["auto", "crew"])
 @pytest.mark.parametrize("threshold", [0, 64, 300])
-def test_dense_batch_takes_the_edge_form(hgm, threshold):
+def test_dense_batch_takes_the_edge_form(hgm, threshold, variant):
     """Dense instances (every vertex of degree about 100), so AUTO's round 0
     takes the edge-centric form over the batch; with a low hub threshold the
-    high-degree vertices become hubs reduced in each workgroup's table."""
+    high-degree vertices become hubs reduced in each workgroup's table
+    (AUTO) or split into pieces in every round (CREW)."""
     rng = np.random.default_rng(23)
     gs = []
     for k in range(24):
@@ -140,8 +142,8 @@ def test_dense_batch_takes_the_edge_form(hgm, threshold):
     b = synth.batch_from_instances(gs, seeds)
     deg = np.concatenate([np.diff(b.instance(i).v_off) for i in range(b.count)])
     assert 2 * int(deg[deg >= 64].sum()) >= int(b.pin_base[-1])   # AUTO's edge-form condition
-    print(f"dense batch hub_threshold={threshold}", flush=True)
-    _check_batch(hgm, b, "auto", hub_threshold=threshold)
+    print(f"dense batch hub_threshold={threshold} variant={variant}", flush=True)
+    _check_batch(hgm, b, variant, hub_threshold=threshold)
 
 
 def test_batch_equals_single_calls(hgm):
