@@ -163,3 +163,22 @@ def test_submit_argument_errors(hgm):
         srv.close()
     assert r["status"] == 0
     assert np.array_equal(r["bits"], oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, 4)[0])
+
+
+@pytest.mark.parametrize("variant,max_batch", [("crew", 0), ("crcw", 1), ("auto", 5)])
+def test_server_variants_and_wave_caps(hgm, pool, variant, max_batch):
+    """The server with other round variants and wave caps (max_batch = 1:
+    one request per wave): every bitmap still equals the oracle's."""
+    exp = _expected(pool)
+    srv = hgm.Server(1 << 30, workers=2, max_batch=max_batch, opts=hgm.make_opts(variant))
+    try:
+        for i, g in enumerate(pool[:16]):
+            srv.submit(g, 1000 + i, req_id=i)
+        res = _drain(srv, 16)
+    finally:
+        srv.close()
+    assert all(r["status"] == 0 for r in res)
+    for r in res:
+        assert np.array_equal(r["bits"], exp[r["id"]]), f"request {r['id']} differs ({variant})"
+    if max_batch:
+        assert max(r["wave_size"] for r in res) <= max_batch
