@@ -191,18 +191,20 @@ State carve(void *ws, const Layout &L, const Opts &o) {
 
 // Rounds to enqueue before the next termination check.  The first batch is
 // sized from kappa: about 0.4 log2(kappa) rounds covered the measured round
-// counts of hash-ordered instances (6 at kappa = 1.4e5 to 11 at 4.8e8)
-// within two.  Afterwards live pins shrink by a factor per round that grows
+// counts of hash-ordered hypergraphs (6 at kappa = 1.4e5 to 11 at 4.8e8)
+// within two; graphs (every edge two pins) finish sooner, and 0.35 log2(kappa)
+// matched Delaunay and random geometric graphs of 2^20 vertices (7 and 8
+// rounds) within one.  Afterwards live pins shrink by a factor per round that grows
 // as the instance thins out, so with the latest factor f the rounds left are
 // at most about log(kappa_r) / log(f); a little over half of that, plus the
 // retire pass that finds the live set empty, matched the measured counts.
 // An unneeded round costs two near-empty launches (about 10 us), a missing
 // one a further host round trip (about 45 us).
-int next_batch(const Opts &o, int launched, const std::vector<int64_t> &live_pins) {
+int next_batch(const Opts &o, int launched, const std::vector<int64_t> &live_pins, bool graph) {
     if (!o.adaptive) return o.rounds_per_sync;
     if (launched == 0 || live_pins.size() < 2) {
         const double k0 = live_pins.empty() ? 2.0 : std::max<double>(2.0, (double)live_pins[0]);
-        const int first = (int)std::lround(0.4 * std::log2(k0));
+        const int first = (int)std::lround((graph ? 0.35 : 0.4) * std::log2(k0));
         return std::max(kFirstBatch, std::min(kAdaptiveMaxBatch, first));
     }
     const double cur = (double)live_pins.back();
@@ -444,7 +446,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     };
     int launched = 0;  // rounds whose test has been enqueued
     while (!finished) {
-        int batch = next_batch(o, launched, live_p);
+        int batch = next_batch(o, launched, live_p, g.kappa == 2 * (int64_t)g.m);
         if (o.max_rounds > 0) batch = std::min(batch, o.max_rounds - launched);
         if (batch <= 0) return HGM_E_ROUND_LIMIT;
         const int first = launched;
