@@ -17,7 +17,10 @@ Printed (one JSON line):
                the committed rocprofv3 PMC summary when it matches the kernel
                source, and traffic_gbs / traffic_frac, that traffic over the
                same average launch time
-  cpu_baseline the oracle's round simulator on the host (one core), same unit
+  cpu_baseline the oracle's greedy on one host core (a child process pinned
+               by taskset): the step's sum of kappa_r over its mean time, so
+               the two values compare as times; the round simulator's rate
+               beside it
   cpu_multicore the OpenMP local max of baselines/ on the host's cores (up
                to 16 threads), same unit
   batched / served  the batched-vs-plain and Poisson-served legs
@@ -301,28 +304,37 @@ def cpu_model() -> str:
     return "unknown CPU"
 
 
-def cpu_baseline(g, seed, budget_s, reseed=False):
+def cpu_baseline(g, seed, budget_s, sum_k, reseed=False):
+    """The oracle on one host core: a child process pinned with taskset to
+    the last core this process may use runs the greedy oracle (key
+    construction, sort, scan; at least three runs, arithmetic mean) and the
+    round simulator once.  `value` is the GPU step's live incidences (sum of
+    kappa_r) over the greedy's mean time, so the ratio of the GPU value to it
+    is the ratio of the times; the round simulator's figure is reported
+    beside it."""
+    import subprocess
+    import tempfile
     import numpy as np
-    import oracle
-    t0 = time.perf_counter()
-    runs = 0
-    stats = None
-    while True:
-        _, stats = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed,
-                                    reseed=reseed)
-        runs += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    t = (time.perf_counter() - t0) / runs
-    tg0 = time.perf_counter()
-    oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, seed)
-    tg = time.perf_counter() - tg0
-    sum_k = int(np.sum(stats["live_pins"]))
+    core = sorted(os.sched_getaffinity(0))[-1]
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "instance.npz")
+        np.savez(path, n=g.n, m=g.m, e_off=g.e_off, e_pins=g.e_pins, v_off=g.v_off,
+                 v_edges=g.v_edges, w=g.w)
+        cmd = ["taskset", "-c", str(core), sys.executable, "-m", "oracle.timing", path,
+               str(seed), str(budget_s), "1" if reseed else "0"]
+        out = subprocess.run(cmd, cwd=ROOT, check=True, capture_output=True, text=True).stdout
+    d = json.loads(out.strip().splitlines()[-1])
+    t = d["greedy_s"]
     return {"value": sum_k / t, "unit": "pin-incidences/s", "cores": 1, "kind": "oracle",
-            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
-            "sample": (f"oracle round simulator (one thread) on the full workload, {runs} run(s) "
-                       f"of {t:.3f} s each, {stats['rounds']} rounds, sum kappa_r = {sum_k}; "
-                       f"oracle greedy on the same input: {tg:.3f} s")}
+            "cpu": d["cpu"], "host_cpus": os.cpu_count(), "pinned_core": core,
+            "allowed_cores": d["allowed_cores"],
+            "simulator_value": d["sum_kappa_r"] / d["simulator_s"],
+            "sample": (f"oracle greedy (key construction, sort, scan) on the full workload, one "
+                       f"thread pinned by taskset to core {core}: {len(d['greedy_runs'])} runs, "
+                       f"mean {t:.3f} s; value = the GPU step's sum of kappa_r ({sum_k}) over "
+                       f"that time.  Oracle round simulator on the same core: "
+                       f"{d['simulator_s']:.3f} s, {d['rounds']} rounds, sum kappa_r = "
+                       f"{d['sum_kappa_r']} (simulator_value)")}
 
 
 def cpu_multicore(g, seed, budget_s, reseed=False):
@@ -521,7 +533,8 @@ def main():
                                       args.serve_budget_gb, args.serve_workers,
                                       edge_side_only=not args.serve_vertex_side)
     if args.cpu_baseline > 0:
-        result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline, bool(args.reseed))
+        result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline, sum_k,
+                                              bool(args.reseed))
     if args.cpu_multicore > 0:
         result["cpu_multicore"] = cpu_multicore(g, seed, args.cpu_multicore, bool(args.reseed))
     print(json.dumps(result), flush=True)

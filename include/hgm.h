@@ -268,9 +268,23 @@ typedef struct hgm_server hgm_server;
 int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *opts,
                       hgm_server **out);
 /* Queues a request (non-blocking, thread-safe).  HGM_E_ARG for negative
- * sizes, kappa >= 2^31 or a NULL array that its sizes require; HGM_E_SIZE when
- * its bitmap alone exceeds a wave's limit (m > 2^31 - 32). */
+ * sizes, kappa >= 2^31, kappa > 0 with m = 0, or a NULL array that its sizes
+ * require; HGM_E_SIZE when its bitmap alone exceeds a wave's limit
+ * (m > 2^31 - 32).  Before its arrays are uploaded, a worker checks the
+ * request's content as hgm_request_check does; a malformed request then
+ * completes with status HGM_E_CSR and never joins a wave, so no kernel of
+ * the wave reads an id outside that request's own arrays. */
 int hgm_server_submit(hgm_server *server, const hgm_request *req);
+
+/* Host-side O(kappa) check of a request's arrays (no GPU needed): e_off
+ * starts at 0, never decreases and ends at kappa; every pin lies in [0, n);
+ * with vertex_side = 1 the same for v_off (ending at kappa) and incident
+ * edge ids in [0, m).  HGM_OK, HGM_E_ARG (sizes or NULL arrays, as
+ * hgm_server_submit) or HGM_E_CSR.  Repeated pins inside an edge and whether
+ * the vertex side is exactly the transpose are not checked (opts->validate
+ * of hgm_match checks both); they cannot make a kernel touch memory outside
+ * the request's own arrays, and only change that request's own result. */
+int hgm_request_check(const hgm_request *req, int32_t vertex_side);
 /* Moves up to `cap` finished results to `out`, waiting up to timeout_s
  * seconds for the first; returns how many were written (or an HGM_E_* code). */
 int hgm_server_poll(hgm_server *server, hgm_result *out, int cap, double timeout_s);
@@ -283,6 +297,10 @@ const char *hgm_strerror(int code);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int hgm_version(void);
+
+/* Digest of the sources and compiler flags the library was built from
+ * (static storage), so that a binding can refuse a stale build. */
+const char *hgm_source_digest(void);
 
 #ifdef __cplusplus
 }

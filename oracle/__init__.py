@@ -203,9 +203,14 @@ def check_maximal(n, m, e_off, e_pins, bits) -> bool:
 
 
 def edge_rank(w, seed, m) -> np.ndarray:
-    """Rank of each edge in the tuple order (w, H(seed,e), e), 0 = lowest."""
+    """Rank of each edge in the tuple order (w, H(seed,e), e), 0 = lowest.
+
+    (w, h) is packed into one unsigned 64-bit word with w in the high half,
+    which orders exactly as the pair; a stable sort then orders equal words
+    by ascending id, the tuple's last component."""
     h = priorities(seed, m)
-    order = np.lexsort((np.arange(m), h, np.asarray(w, dtype=np.uint32)))
+    wh = (np.asarray(w, dtype=np.uint64) << np.uint64(32)) | h.astype(np.uint64)
+    order = np.argsort(wh, kind="stable")
     rank = np.empty(m, dtype=np.int64)
     rank[order] = np.arange(m, dtype=np.int64)
     return rank
@@ -230,8 +235,13 @@ def check_greedy_certificate(n, m, e_off, e_pins, w, seed, bits) -> bool:
     cover = np.full(n, -1, dtype=np.int64)
     mi = matched[eid]
     cover[pins[mi]] = rank[eid[mi]]
+    # best_cover[e] = highest rank of a matched edge at a pin of e (-1: none)
+    sizes = np.diff(np.asarray(e_off, dtype=np.int64))
     best_cover = np.full(m, -1, dtype=np.int64)
-    np.maximum.at(best_cover, eid, cover[pins])
+    nz = sizes > 0
+    if pins.size:
+        starts = np.asarray(e_off, dtype=np.int64)[:-1][nz]
+        best_cover[nz] = np.maximum.reduceat(cover[pins], starts)
     unmatched = ~matched
     return bool(np.all(best_cover[unmatched] > rank[unmatched]))
 

@@ -27,7 +27,8 @@ VARIANTS = {"auto": HGM_VARIANT_AUTO, "crcw": HGM_VARIANT_CRCW, "crew": HGM_VARI
 
 EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_batch_workspace_size", "hgm_match_batch",
             "hgm_server_create", "hgm_server_submit", "hgm_server_poll", "hgm_server_info",
-            "hgm_server_destroy", "hgm_strerror", "hgm_version"]
+            "hgm_server_destroy", "hgm_request_check", "hgm_strerror", "hgm_version",
+            "hgm_source_digest"]
 
 
 class HgmCsr(ctypes.Structure):
@@ -103,15 +104,23 @@ _lib = None
 
 
 def load():
-    """Load libhgm.so; raises if it has not been built."""
+    """Load libhgm.so; raises if it has not been built, or if it was built
+    from other sources than the ones beside it (a stale build)."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "paper_2602_22976_amd.build.build() (hipcc, gfx950)")
+    from . import build as _build
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
+    lib.hgm_source_digest.restype = ctypes.c_char_p
+    lib.hgm_source_digest.argtypes = []
+    built, want = lib.hgm_source_digest().decode(), _build.source_digest()
+    if built != want:
+        raise RuntimeError(f"{LIB_PATH} was built from other sources (digest {built}, sources "
+                           f"{want}): rebuild it with paper_2602_22976_amd.build.build()")
     lib.hgm_workspace_size.restype = ctypes.c_size_t
     lib.hgm_workspace_size.argtypes = [ctypes.POINTER(HgmCsr), ctypes.POINTER(HgmOpts)]
     lib.hgm_match.restype = ctypes.c_int
@@ -133,6 +142,8 @@ def load():
     lib.hgm_server_info.argtypes = [P, ctypes.POINTER(HgmServerState)]
     lib.hgm_server_destroy.restype = ctypes.c_int
     lib.hgm_server_destroy.argtypes = [P]
+    lib.hgm_request_check.restype = ctypes.c_int
+    lib.hgm_request_check.argtypes = [ctypes.POINTER(HgmRequest), ctypes.c_int32]
     lib.hgm_strerror.restype = ctypes.c_char_p
     lib.hgm_strerror.argtypes = [ctypes.c_int]
     lib.hgm_version.restype = ctypes.c_int
@@ -367,6 +378,30 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
 # ---------------------------------------------------------------------------
 # Request server (hgm_server_*): marshalling and bookkeeping of host buffers.
 
+def request(g, seed, rid=0, vertex_side=True):
+    """An HgmRequest over host hypergraph `g` (numpy arrays); returns
+    (request, arrays it points into, output bitmap).  The arrays must stay
+    alive while the request is in use."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(g.e_off, dtype=np.int32),
+            np.ascontiguousarray(g.e_pins, dtype=np.int32),
+            np.ascontiguousarray(g.v_off, dtype=np.int32) if vertex_side else None,
+            np.ascontiguousarray(g.v_edges, dtype=np.int32) if vertex_side else None,
+            np.ascontiguousarray(g.w, dtype=np.uint32)]
+    out = np.zeros(max((g.m + 31) // 32, 1), dtype=np.uint32)
+    q = HgmRequest()
+    q.id, q.n, q.m, q.kappa = rid, g.n, g.m, int(arrs[1].size)
+    q.e_off, q.e_pins, q.v_off, q.v_edges, q.w = [
+        a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs]
+    q.seed = seed & 0xFFFFFFFF
+    q.bits_out = out.ctypes.data_as(ctypes.c_void_p)
+    return q, arrs, out
+
+
+def hgm_request_check(q: HgmRequest, vertex_side: bool = True) -> int:
+    """Raw call; returns the HGM_* code of the host-side content check."""
+    return int(load().hgm_request_check(ctypes.byref(q), 1 if vertex_side else 0))
+
 class Server:
     """Continuous-batching request server over a torch-allocated device arena.
 
@@ -394,22 +429,15 @@ class Server:
         self.next_id = 0
 
     def submit(self, g, seed, req_id=None):
-        import numpy as np
+        """Queue a matching of host hypergraph `g`; returns its id.  A given
+        req_id must not belong to a request whose result is not yet polled:
+        the server writes each result into buffers kept under its id."""
         rid = self.next_id if req_id is None else int(req_id)
-        self.next_id = max(self.next_id, rid) + 1
+        if rid in self.live:
+            raise ValueError(f"request id {rid} is still in flight")
         vside = not self.edge_side_only   # else the vertex side is not sent
-        arrs = [np.ascontiguousarray(g.e_off, dtype=np.int32),
-                np.ascontiguousarray(g.e_pins, dtype=np.int32),
-                np.ascontiguousarray(g.v_off, dtype=np.int32) if vside else None,
-                np.ascontiguousarray(g.v_edges, dtype=np.int32) if vside else None,
-                np.ascontiguousarray(g.w, dtype=np.uint32)]
-        out = np.zeros(max((g.m + 31) // 32, 1), dtype=np.uint32)
-        q = HgmRequest()
-        q.id, q.n, q.m, q.kappa = rid, g.n, g.m, int(arrs[1].size)
-        q.e_off, q.e_pins, q.v_off, q.v_edges, q.w = [
-            a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs]
-        q.seed = seed & 0xFFFFFFFF
-        q.bits_out = out.ctypes.data_as(ctypes.c_void_p)
+        q, arrs, out = request(g, seed, rid, vside)
+        self.next_id = max(self.next_id, rid) + 1
         self.live[rid] = (arrs, out, g.m)
         rc = load().hgm_server_submit(self.h, ctypes.byref(q))
         if rc != HGM_OK:

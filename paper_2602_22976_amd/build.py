@@ -1,4 +1,9 @@
-"""Builds libhgm.so (the HIP library behind include/hgm.h) for gfx950."""
+"""Builds libhgm.so (the HIP library behind include/hgm.h) for gfx950.
+
+The library carries a digest of the sources and flags it was built from
+(hgm_source_digest); the binding refuses a library whose digest differs
+from the sources beside it, so a stale build is never run."""
+import hashlib
 import os
 import shutil
 import subprocess
@@ -17,10 +22,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-pthread",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def source_digest() -> str:
+    """SHA-256 (first 16 hex digits) over the library's sources, the headers
+    they include and the compiler flags."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for fn in files:
+        h.update(fn.encode())
+        with open(os.path.join(CSRC, fn), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(ROOT, "include", "hgm.h"), "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(FLAGS + SOURCES).encode())
+    return h.hexdigest()[:16]
+
+
 def command(out: str):
-    return [hipcc(), "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-pthread",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out] + \
+    return [hipcc()] + FLAGS + [f'-DHGM_SOURCE_DIGEST="{source_digest()}"',
+                                "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out] + \
            [os.path.join(CSRC, s) for s in SOURCES]
 
 

@@ -532,7 +532,12 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
 
 extern "C" {
 
-int hgm_version(void) { return 300; }
+int hgm_version(void) { return 400; }
+
+#ifndef HGM_SOURCE_DIGEST
+#define HGM_SOURCE_DIGEST "unknown"
+#endif
+const char *hgm_source_digest(void) { return HGM_SOURCE_DIGEST; }
 
 const char *hgm_strerror(int code) {
     switch (code) {

@@ -160,6 +160,41 @@ WaveLayout wave_layout(int count, int64_t n, int64_t m, int64_t kappa, int64_t w
 
 size_t words_of(int32_t m) { return ((size_t)m + 31) / 32; }
 
+// off[0] = 0, off[i] <= off[i + 1], off[count] = total.  The loop keeps no
+// early exit so that the compiler vectorises it.
+bool offsets_ok(const int32_t *off, int64_t count, int64_t total) {
+    if (off[0] != 0 || (int64_t)off[count] != total) return false;
+    int bad = 0;
+    for (int64_t i = 0; i < count; ++i) bad |= off[i + 1] < off[i];
+    return bad == 0;
+}
+
+// Every id in [0, limit).
+bool ids_ok(const int32_t *ids, int64_t len, int32_t limit) {
+    uint32_t bad = 0;
+    for (int64_t i = 0; i < len; ++i) bad |= (uint32_t)ids[i] >= (uint32_t)limit;
+    return bad == 0;
+}
+
+// Size and NULL checks of a request (O(1)).
+int request_args(const hgm_request &q, bool vside) {
+    if (q.n < 0 || q.m < 0 || q.kappa < 0 || q.kappa >= ((int64_t)1 << 31)) return HGM_E_ARG;
+    if ((q.m > 0 && (!q.e_off || !q.w || !q.bits_out)) || (q.kappa > 0 && !q.e_pins))
+        return HGM_E_ARG;
+    if (q.kappa > 0 && q.m == 0) return HGM_E_ARG;
+    if (vside && (!q.v_off || (q.kappa > 0 && (!q.v_edges || q.n == 0)))) return HGM_E_ARG;
+    return HGM_OK;
+}
+
+// O(kappa) content check (see hgm_request_check).
+int request_content(const hgm_request &q, bool vside) {
+    if (q.m > 0 && (!offsets_ok(q.e_off, q.m, q.kappa) || !ids_ok(q.e_pins, q.kappa, q.n)))
+        return HGM_E_CSR;
+    if (vside && (!offsets_ok(q.v_off, q.n, q.kappa) || !ids_ok(q.v_edges, q.kappa, q.m)))
+        return HGM_E_CSR;
+    return HGM_OK;
+}
+
 // A wave is one hgm_match_batch call, whose totals of vertices, edges, pins
 // and bitmap bits are 32-bit.
 constexpr int64_t kWaveLimit = ((int64_t)1 << 31) - 1;
@@ -342,13 +377,37 @@ void worker_main(hgm_server *S, hipStream_t stream) {
             t_admit = now_s();
         }
         S->cv_work.notify_all();  // the next worker may form the next wave now
-        const int rc = run_wave(S, stream, wave, off, L, n, m, kappa, words);
+        // Content check of every request before its arrays are uploaded: a
+        // malformed request completes with HGM_E_CSR and never joins the
+        // wave, so no kernel reads ids outside its own request.  The rest
+        // run in a layout recomputed for them, which is no larger than the
+        // block reserved for the whole wave.
+        std::vector<Pending> good, bad;
+        for (const Pending &p : wave)
+            (request_content(p.req, !S->opts.edge_side_only) == HGM_OK ? good : bad).push_back(p);
+        if (!bad.empty()) finish(S, bad, HGM_E_CSR, t_admit);
+        int rc = HGM_OK;
+        if (!good.empty()) {
+            if (!bad.empty()) {
+                n = m = kappa = words = 0;
+                for (const Pending &p : good) {
+                    n += p.req.n;
+                    m += p.req.m;
+                    kappa += p.req.kappa;
+                    words += (int64_t)words_of(p.req.m);
+                }
+            }
+            const WaveLayout G =
+                bad.empty() ? L : wave_layout((int)good.size(), n, m, kappa, words, S->opts);
+            rc = G.total <= L.total ? run_wave(S, stream, good, off, G, n, m, kappa, words)
+                                    : HGM_E_SIZE;
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->arena.release(off, L.total);
         }
         S->cv_work.notify_all();
-        finish(S, wave, rc, t_admit);
+        if (!good.empty()) finish(S, good, rc, t_admit);
     }
 }
 
@@ -391,11 +450,9 @@ int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *op
 int hgm_server_submit(hgm_server *S, const hgm_request *req) {
     if (!S || !req) return HGM_E_ARG;
     const hgm_request &q = *req;
-    if (q.n < 0 || q.m < 0 || q.kappa < 0 || q.kappa >= ((int64_t)1 << 31)) return HGM_E_ARG;
+    const int rc = request_args(q, !S->opts.edge_side_only);
+    if (rc != HGM_OK) return rc;
     if (32 * (int64_t)words_of(q.m) > kWaveLimit) return HGM_E_SIZE;
-    if ((q.m > 0 && (!q.e_off || !q.w || !q.bits_out)) || (q.kappa > 0 && !q.e_pins))
-        return HGM_E_ARG;
-    if (!S->opts.edge_side_only && (!q.v_off || (q.kappa > 0 && !q.v_edges))) return HGM_E_ARG;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) return HGM_E_ARG;
     S->queue.push_back(Pending{q, now_s()});
@@ -428,6 +485,13 @@ int hgm_server_info(hgm_server *S, hgm_server_state *st) {
     st->arena_used = S->arena.used();
     st->arena_peak = S->arena.peak();
     return HGM_OK;
+}
+
+int hgm_request_check(const hgm_request *req, int32_t vertex_side) {
+    if (!req || (vertex_side != 0 && vertex_side != 1)) return HGM_E_ARG;
+    const int rc = request_args(*req, vertex_side != 0);
+    if (rc != HGM_OK) return rc;
+    return request_content(*req, vertex_side != 0);
 }
 
 int hgm_server_destroy(hgm_server *S) {

@@ -8,9 +8,9 @@ compressed form; it performs none of the matching arithmetic.
 from .gen import (Batch, Hypergraph, batch_from_instances, config_batched, config_delaunay,
                   config_hub_stress, config_plain, config_power_law, config_rgg,
                   config_served_pool, from_edge_lists, from_pairs, random_instance, rgg_pairs,
-                  transpose)
+                  shuffle_batch, shuffle_lists, transpose)
 
 __all__ = ["Batch", "Hypergraph", "batch_from_instances", "config_batched", "config_delaunay",
            "config_hub_stress", "config_plain", "config_power_law", "config_rgg",
            "config_served_pool", "from_edge_lists", "from_pairs", "random_instance", "rgg_pairs",
-           "transpose"]
+           "shuffle_batch", "shuffle_lists", "transpose"]

@@ -357,3 +357,31 @@ def config_rgg(seed: int = 1007, n: int = 1 << 20) -> Hypergraph:
     r = 0.55 * math.sqrt(math.log(n) / n)
     pairs = rgg_pairs(pts, r)
     return from_pairs(n, pairs, np.ones(pairs.shape[0], dtype=np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# List order.  The generators above list pins and incident edges in ascending
+# order; the interface accepts any order inside a list.  These helpers draw a
+# seeded random order inside every list (the sets are unchanged).
+
+def _shuffle_segments(rng, off: np.ndarray, vals: np.ndarray) -> np.ndarray:
+    off = np.asarray(off, dtype=np.int64)
+    sizes = np.diff(off)
+    seg = np.repeat(np.arange(sizes.shape[0], dtype=np.int64), sizes)
+    order = np.lexsort((rng.random(vals.shape[0]), seg))
+    return np.ascontiguousarray(np.asarray(vals)[order])
+
+
+def shuffle_lists(g: Hypergraph, seed: int) -> Hypergraph:
+    """The same hypergraph with pins in a random order inside every edge and
+    incident edges in a random order inside every vertex list."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = Hypergraph(g.n, g.m, g.e_off.copy(), _shuffle_segments(rng, g.e_off, g.e_pins),
+                     g.v_off.copy(), _shuffle_segments(rng, g.v_off, g.v_edges), g.w.copy())
+    return out
+
+
+def shuffle_batch(b: Batch, seed: int) -> Batch:
+    """shuffle_lists applied to every instance of a batch."""
+    graphs = [shuffle_lists(b.instance(i), seed + i) for i in range(b.count)]
+    return batch_from_instances(graphs, b.seeds)

@@ -181,3 +181,59 @@ def test_server_arguments_without_gpu(lib):
     assert lib.hgm_server_poll(None, None, 0, 0.0) == hgm.HGM_E_ARG
     assert lib.hgm_server_info(None, None) == hgm.HGM_E_ARG
     assert lib.hgm_server_destroy(None) == hgm.HGM_E_ARG
+
+
+def test_request_check_without_gpu(lib):
+    """hgm_request_check (the server's pre-upload check) on host arrays:
+    well-formed requests pass, and each kind of malformed offset or id is
+    rejected with HGM_E_CSR before any upload."""
+    import numpy as np
+    import synth
+    g = synth.random_instance(5, 40, 60, 0, 6, 1, 9, empty_frac=0.1)
+    for vside in (True, False):
+        q, keep, _ = hgm.request(g, 1, 0, vside)
+        assert hgm.hgm_request_check(q, vside) == hgm.HGM_OK
+
+    def bad(field, mutate, vside=True):
+        arrays = {k: getattr(g, k).copy() for k in ("e_off", "e_pins", "v_off", "v_edges", "w")}
+        mutate(arrays[field])
+        h = synth.Hypergraph(g.n, g.m, **arrays)
+        q, keep, _ = hgm.request(h, 1, 0, vside)
+        q.kappa = g.kappa
+        return hgm.hgm_request_check(q, vside)
+
+    def set_at(i, v):
+        def f(a):
+            a[i] = v
+        return f
+
+    k = g.kappa
+    assert bad("e_off", set_at(0, 1)) == hgm.HGM_E_CSR              # does not start at 0
+    assert bad("e_off", set_at(g.m, k - 1)) == hgm.HGM_E_CSR        # does not end at kappa
+    i = int(np.flatnonzero(np.diff(g.e_off) > 1)[0]) + 1
+    assert bad("e_off", set_at(i, int(g.e_off[i - 1]) - 1)) == hgm.HGM_E_CSR  # decreases
+    assert bad("e_pins", set_at(3, g.n)) == hgm.HGM_E_CSR           # pin out of range
+    assert bad("e_pins", set_at(7, -1)) == hgm.HGM_E_CSR
+    assert bad("v_off", set_at(g.n, k + 1)) == hgm.HGM_E_CSR
+    assert bad("v_edges", set_at(2, g.m)) == hgm.HGM_E_CSR          # edge id out of range
+    assert bad("v_edges", set_at(2, g.m), vside=False) == hgm.HGM_OK  # vertex side not read
+    # size and NULL errors
+    q, keep, _ = hgm.request(g, 1, 0, True)
+    q.n = -1
+    assert hgm.hgm_request_check(q, True) == hgm.HGM_E_ARG
+    q, keep, _ = hgm.request(g, 1, 0, False)
+    assert hgm.hgm_request_check(q, True) == hgm.HGM_E_ARG          # vertex side missing
+    assert lib.hgm_request_check(None, 1) == hgm.HGM_E_ARG
+
+
+def test_server_rejects_duplicate_live_id():
+    """A caller's id that is still in flight is refused before the C call
+    (its result buffers are kept under that id)."""
+    import synth
+    srv = hgm.Server.__new__(hgm.Server)
+    srv.live = {7: None}
+    srv.next_id = 8
+    srv.edge_side_only = False
+    with pytest.raises(ValueError):
+        srv.submit(synth.random_instance(1, 10, 10), 1, req_id=7)
+    srv.h = None

@@ -2,6 +2,8 @@
 oracle's greedy matching for that instance and seed, and equals hgm_match on
 the instance alone; the aggregate per-round counts equal the sum of the
 instances' oracle round counts."""
+import time
+
 import numpy as np
 import pytest
 
@@ -175,8 +177,9 @@ def test_batch_full_workload(hgm):
     """The full batched workload that bench.py times (4,096 instances, sum of
     kappa about 4.8e8, one launch): a seeded sample of instances, with the
     largest and the smallest, equals the oracle bit for bit; every instance's
-    segment is a maximal matching, checked over the whole concatenation with
-    instance-global vertex ids; the totals add up."""
+    segment passes the greedy certificate (which only the oracle's matching
+    passes) and is a maximal matching, checked over the whole concatenation
+    with instance-global vertex ids; the totals add up."""
     import torch
     b = synth.config_batched(seed=1004, count=4096)
     kap = np.diff(b.pin_base)
@@ -197,6 +200,15 @@ def test_batch_full_workload(hgm):
         g = b.instance(i)
         exp = oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, int(b.seeds[i]))[0]
         assert np.array_equal(segs[i], exp), f"instance {i} differs"
+    # Every instance: the greedy certificate (a matching in which every
+    # unmatched edge has a matched neighbour ranked above it) holds for
+    # exactly one edge set, the greedy matching of the instance's order.
+    t0 = time.time()
+    for i in range(b.count):
+        g = b.instance(i)
+        assert oracle.check_greedy_certificate(g.n, g.m, g.e_off, g.e_pins, g.w,
+                                               int(b.seeds[i]), segs[i]), f"instance {i}"
+    print(f"greedy certificate on all {b.count} instances: {time.time() - t0:.1f} s", flush=True)
 
     matched = np.concatenate([oracle.bits_to_bool(segs[i], int(b.m[i])) for i in range(b.count)])
     sizes = np.concatenate([np.diff(b.e_off[b.e_base[i] + i: b.e_base[i + 1] + i + 1])

@@ -182,3 +182,64 @@ def test_server_variants_and_wave_caps(hgm, pool, variant, max_batch):
         assert np.array_equal(r["bits"], exp[r["id"]]), f"request {r['id']} differs ({variant})"
     if max_batch:
         assert max(r["wave_size"] for r in res) <= max_batch
+
+
+def _served_request(seed, kappa):
+    """A request of the served workload's shape with about `kappa` pins:
+    |e| ~ U{2..32}, m = round(kappa / 17), n = max(32, round(m / 2)),
+    w ~ U{1..1e6}."""
+    m = max(1, round(kappa / 17))
+    return synth.random_instance(seed, max(32, round(m / 2)), m, 2, 32, 1, 1_000_000)
+
+
+@pytest.mark.parametrize("edge_side_only", [True, False])
+def test_large_requests_served_range(hgm, pool, edge_side_only):
+    """Requests across the served workload's whole kappa range [1e3, 1e7]:
+    three large ones (kappa about 1e6, 3e6 and 1e7) submitted among small
+    ones; every bitmap equals the oracle's."""
+    big = [_served_request(901, 1e6), _served_request(902, 3e6), _served_request(903, 1e7)]
+    print("large requests kappa=" + ",".join(str(g.kappa) for g in big), flush=True)
+    reqs = big[:1] + pool[:8] + big[1:2] + pool[8:16] + big[2:]
+    srv = hgm.Server(4 << 30, workers=3, edge_side_only=edge_side_only)
+    try:
+        for i, g in enumerate(reqs):
+            srv.submit(g, 7000 + i, req_id=i)
+        res = _drain(srv, len(reqs), timeout=300)
+        info = srv.info()
+    finally:
+        srv.close()
+    assert info["arena_peak"] <= info["arena_bytes"]
+    for r in res:
+        g = reqs[r["id"]]
+        assert r["status"] == 0
+        exp = oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, 7000 + r["id"])[0]
+        assert np.array_equal(r["bits"], exp), f"request {r['id']} (kappa {g.kappa}) differs"
+
+
+@pytest.mark.parametrize("edge_side_only", [True, False])
+def test_malformed_request_fails_alone(hgm, pool, edge_side_only):
+    """A request with a pin out of range, or offsets that do not end at
+    kappa, completes with HGM_E_CSR before upload; the requests submitted
+    around it, which may share its wave, still equal the oracle."""
+    exp = _expected(pool)
+    bad_pin = synth.random_instance(4, 100, 80, 2, 6, 1, 9)
+    bad_pin.e_pins = bad_pin.e_pins.copy()
+    bad_pin.e_pins[5] = bad_pin.n + 3
+    bad_off = synth.random_instance(5, 100, 80, 2, 6, 1, 9)
+    bad_off.e_off = bad_off.e_off.copy()
+    bad_off.e_off[40] = bad_off.e_off[39] - 1
+    srv = hgm.Server(1 << 30, workers=1, edge_side_only=edge_side_only)
+    try:
+        for i in range(12):
+            srv.submit(pool[i], 1000 + i, req_id=i)
+        srv.submit(bad_pin, 1, req_id=100)
+        srv.submit(bad_off, 1, req_id=101)
+        for i in range(12, 20):
+            srv.submit(pool[i], 1000 + i, req_id=i)
+        res = {r["id"]: r for r in _drain(srv, 22)}
+    finally:
+        srv.close()
+    assert res[100]["status"] == hgm.HGM_E_CSR and res[101]["status"] == hgm.HGM_E_CSR
+    for i in range(20):
+        assert res[i]["status"] == 0
+        assert np.array_equal(res[i]["bits"], exp[i]), i

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import random_instance
+from synth import from_edge_lists, random_instance
 from tests.fixtures import disjoint, golden_files, path_graph, read_golden, star
 
 M32 = 0xFFFFFFFF
@@ -379,3 +379,56 @@ def test_reseed_many_small_instances_valid():
         assert oracle.check_matching(g.n, g.m, g.e_off, g.e_pins, bits)
         assert oracle.check_maximal(g.n, g.m, g.e_off, g.e_pins, bits)
         _stats_invariants(g, bits, st)
+
+
+def _murmur_id(seed, x):
+    """H(seed, x) from the byte-string MurmurHash3 (pinned by published vectors)."""
+    return oracle.murmur3_x86_32(int(x).to_bytes(4, "little"), seed)
+
+
+def _tie_winner(seed, rnd, a, b):
+    """The edge of {a, b} (equal weights) that round `rnd` ranks higher:
+    larger H(H(seed, rnd), e)."""
+    rs = _murmur_id(seed, rnd)
+    return a if _murmur_id(rs, a) > _murmur_id(rs, b) else b
+
+
+def test_reseed_round_one_tie_uses_round_one_priorities():
+    """Hand-derived: h = {u,t} (w 3) is matched in round 0 and retires
+    g = {y,u} (w 2), which had blocked the equal-weight pair f1 = {x,y},
+    f2 = {y,z} at y.  The pair first meets at y with no heavier edge in
+    round 1, so round 1's priorities H(H(seed, 1), .) decide it.  Over 40
+    seeds round 0's priorities pick the other edge in 17 cases, so an oracle
+    that kept round 0's order would fail here."""
+    u, t, y, x, z = range(5)
+    g = from_edge_lists(5, [[u, t], [y, u], [x, y], [y, z]], [3, 2, 1, 1])
+    disagree = 0
+    for seed in range(40):
+        win = _tie_winner(seed, 1, 2, 3)
+        disagree += win != _tie_winner(seed, 0, 2, 3)
+        bits, st = _lm(g, seed)
+        assert list(np.flatnonzero(oracle.bits_to_bool(bits, g.m))) == sorted([0, win]), seed
+        assert st["rounds"] == 2
+        assert list(st["live_edges"]) == [4, 2] and list(st["matched_per_round"]) == [1, 1]
+        assert list(st["live_pins"]) == [8, 4]
+    assert disagree > 0
+
+
+def test_reseed_round_two_tie_uses_round_two_priorities():
+    """Hand-derived three-round chain: Y = {p,q} (w 5) matches in round 0 and
+    retires X = {t,q} (w 4); X had beaten h = {u,t} (w 3) at t, so h matches
+    in round 1 and retires g = {y,u} (w 2); g had beaten the equal-weight
+    pair f1 = {x,y}, f2 = {y,z} at y until then, so round 2's priorities
+    H(H(seed, 2), .) decide the pair."""
+    p, q, t, u, y, x, z = range(7)
+    g = from_edge_lists(7, [[p, q], [t, q], [u, t], [y, u], [x, y], [y, z]], [5, 4, 3, 2, 1, 1])
+    disagree = 0
+    for seed in range(40):
+        win = _tie_winner(seed, 2, 4, 5)
+        disagree += win != _tie_winner(seed, 1, 4, 5) or win != _tie_winner(seed, 0, 4, 5)
+        bits, st = _lm(g, seed)
+        assert list(np.flatnonzero(oracle.bits_to_bool(bits, g.m))) == sorted([0, 2, win]), seed
+        assert st["rounds"] == 3
+        assert list(st["live_edges"]) == [6, 4, 2]
+        assert list(st["matched_per_round"]) == [1, 1, 1]
+    assert disagree > 0

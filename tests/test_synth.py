@@ -92,3 +92,39 @@ def test_rgg_graph_shape():
     _well_formed(g, 2, 2)
     mean_deg = 2 * g.m / n
     assert abs(mean_deg - 0.95 * np.log(n)) < 1.5   # pi (0.55)^2 ln n, less at the border
+
+
+def test_shuffle_lists_keeps_sets_and_results():
+    """Shuffling the order inside every list keeps each edge's pin set and
+    each vertex's edge set, and the oracle's results do not change."""
+    import oracle
+    g = synth.random_instance(12, 300, 900, 1, 9, 1, 4, empty_frac=0.02)
+    s = synth.shuffle_lists(g, 3)
+    assert np.array_equal(s.e_off, g.e_off) and np.array_equal(s.v_off, g.v_off)
+    assert not np.array_equal(s.e_pins, g.e_pins)
+    for e in range(g.m):
+        a, b = g.e_off[e], g.e_off[e + 1]
+        assert sorted(g.e_pins[a:b]) == sorted(s.e_pins[a:b])
+    for v in range(g.n):
+        a, b = g.v_off[v], g.v_off[v + 1]
+        assert sorted(g.v_edges[a:b]) == sorted(s.v_edges[a:b])
+    for seed in (1, 2):
+        assert np.array_equal(oracle.greedy(g.n, g.m, g.e_off, g.e_pins, g.w, seed)[0],
+                              oracle.greedy(s.n, s.m, s.e_off, s.e_pins, s.w, seed)[0])
+        for reseed in (False, True):
+            a = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed,
+                                 reseed=reseed)
+            b = oracle.local_max(s.n, s.m, s.e_off, s.e_pins, s.v_off, s.v_edges, s.w, seed,
+                                 reseed=reseed)
+            assert np.array_equal(a[0], b[0]) and a[1]["rounds"] == b[1]["rounds"]
+
+
+def test_shuffle_batch_per_instance():
+    b = synth.config_batched(seed=3, count=5, n_hi=300)
+    s = synth.shuffle_batch(b, 1)
+    assert np.array_equal(s.pin_base, b.pin_base) and np.array_equal(s.seeds, b.seeds)
+    for i in range(b.count):
+        gi, si = b.instance(i), s.instance(i)
+        for e in range(gi.m):
+            a, c = gi.e_off[e], gi.e_off[e + 1]
+            assert sorted(gi.e_pins[a:c]) == sorted(si.e_pins[a:c])
