@@ -267,10 +267,10 @@ typedef struct hgm_server hgm_server;
  * HGM_E_HIP when the workers' streams cannot be created. */
 int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *opts,
                       hgm_server **out);
-/* Queues a request (non-blocking, thread-safe).  HGM_E_ARG for negative
- * sizes, kappa >= 2^31, kappa > 0 with m = 0, or a NULL array that its sizes
- * require; HGM_E_SIZE when its bitmap alone exceeds a wave's limit
- * (m > 2^31 - 32).  Before its arrays are uploaded, a worker checks the
+/* Queues a request (non-blocking, thread-safe).  HGM_E_SIZE when its bitmap
+ * alone exceeds a wave's limit (m > 2^31 - 32; checked first); else
+ * HGM_E_ARG for negative sizes, kappa >= 2^31, kappa > 0 with m = 0, or a
+ * NULL array that its sizes require.  Before its arrays are uploaded, a worker checks the
  * request's content as hgm_request_check does; a malformed request then
  * completes with status HGM_E_CSR and never joins a wave, so no kernel of
  * the wave reads an id outside that request's own arrays. */

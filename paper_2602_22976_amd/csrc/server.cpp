@@ -450,9 +450,11 @@ int hgm_server_create(void *arena, size_t arena_bytes, const hgm_server_opts *op
 int hgm_server_submit(hgm_server *S, const hgm_request *req) {
     if (!S || !req) return HGM_E_ARG;
     const hgm_request &q = *req;
+    // A bitmap larger than any wave can hold is a size error whatever else
+    // the request carries.
+    if (q.m > 0 && 32 * (int64_t)words_of(q.m) > kWaveLimit) return HGM_E_SIZE;
     const int rc = request_args(q, !S->opts.edge_side_only);
     if (rc != HGM_OK) return rc;
-    if (32 * (int64_t)words_of(q.m) > kWaveLimit) return HGM_E_SIZE;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stopping) return HGM_E_ARG;
     S->queue.push_back(Pending{q, now_s()});
