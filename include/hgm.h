@@ -160,6 +160,25 @@ size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts);
 int hgm_match(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits, void *workspace,
               size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats);
 
+/* hgm_match without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a fixed array of
+ * hgm_noalloc_max_bytes() bytes (64 MiB) in the library's own device memory,
+ * one per GPU, held from the library's load until the process ends; its
+ * address is looked up on the first call on each device.  The entry point
+ * calls no hipMalloc / hipFree or other allocating routine.
+ *   Arguments, results and errors as hgm_match, plus: HGM_E_SIZE when the
+ * instance needs more workspace than the array holds (hgm_workspace_size()
+ * > hgm_noalloc_max_bytes()); HGM_E_ARG for stats->timing = 1 (timing
+ * creates HIP events).  Every call on one GPU uses that GPU's one array and
+ * leaves its contents behind (the next call clears what it needs), so calls
+ * that overlap on one GPU -- on different streams or threads -- race and
+ * must be serialised by the caller. */
+int hgm_match_noalloc(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits,
+                      const hgm_opts *opts, void *stream, hgm_stats *stats);
+/* Size in bytes of hgm_match_noalloc's per-GPU workspace array. */
+size_t hgm_noalloc_max_bytes(void);
+
 /* A batch of independent hypergraphs matched in one call.  Instances keep
  * their own (local) ids, so instance i's slices are byte-identical to its
  * standalone hgm_csr; all arrays are the instances' arrays concatenated in

@@ -28,7 +28,7 @@ VARIANTS = {"auto": HGM_VARIANT_AUTO, "crcw": HGM_VARIANT_CRCW, "crew": HGM_VARI
 EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_batch_workspace_size", "hgm_match_batch",
             "hgm_server_create", "hgm_server_submit", "hgm_server_poll", "hgm_server_info",
             "hgm_server_destroy", "hgm_request_check", "hgm_strerror", "hgm_version",
-            "hgm_source_digest"]
+            "hgm_source_digest", "hgm_match_noalloc", "hgm_noalloc_max_bytes"]
 
 
 class HgmCsr(ctypes.Structure):
@@ -126,6 +126,11 @@ def load():
     lib.hgm_match.restype = ctypes.c_int
     lib.hgm_match.argtypes = [ctypes.POINTER(HgmCsr), ctypes.c_uint32, P, P, ctypes.c_size_t,
                               ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
+    lib.hgm_match_noalloc.restype = ctypes.c_int
+    lib.hgm_match_noalloc.argtypes = [ctypes.POINTER(HgmCsr), ctypes.c_uint32, P,
+                                      ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
+    lib.hgm_noalloc_max_bytes.restype = ctypes.c_size_t
+    lib.hgm_noalloc_max_bytes.argtypes = []
     lib.hgm_batch_workspace_size.restype = ctypes.c_size_t
     lib.hgm_batch_workspace_size.argtypes = [ctypes.POINTER(HgmBatch), ctypes.POINTER(HgmOpts)]
     lib.hgm_match_batch.restype = ctypes.c_int
@@ -174,6 +179,19 @@ def hgm_match(csr: HgmCsr, seed: int, bits_ptr: int, ws_ptr: int, ws_bytes: int,
                                 ctypes.byref(opts) if opts is not None else None,
                                 stream or None,
                                 ctypes.byref(stats) if stats is not None else None))
+
+
+def hgm_match_noalloc(csr: HgmCsr, seed: int, bits_ptr: int, opts: HgmOpts | None = None,
+                      stream: int = 0, stats: HgmStats | None = None) -> int:
+    """Raw call; returns the HGM_* code."""
+    return int(load().hgm_match_noalloc(ctypes.byref(csr), seed & 0xFFFFFFFF, bits_ptr or None,
+                                        ctypes.byref(opts) if opts is not None else None,
+                                        stream or None,
+                                        ctypes.byref(stats) if stats is not None else None))
+
+
+def hgm_noalloc_max_bytes() -> int:
+    return int(load().hgm_noalloc_max_bytes())
 
 
 def hgm_batch_workspace_size(batch: HgmBatch, opts: HgmOpts | None = None) -> int:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "hgm.h"
@@ -528,6 +529,68 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
 }
 
 
+// Workspace of hgm_match_noalloc: one array per GPU in the library's device
+// memory, held until the process ends.  In host code `scratch` names a host
+// stand-in, not the device array, so the array is only ever used through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];  // zero-initialised (static storage)
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current), or NULL on a HIP error.
+void *scratch_address() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (p) return p;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
+    return p;
+}
+
+// Shared body of hgm_match and hgm_match_noalloc.
+int match_one(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *workspace,
+              size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats) {
+    Opts o;
+    int rc = resolve_opts(opts, &o);
+    if (rc != HGM_OK) return rc;
+    rc = check_graph(gin, o);
+    if (rc != HGM_OK) return rc;
+    bind_graph(&o, gin);
+    if (gin->m > 0 && !matched_bits) return HGM_E_ARG;
+    if (stats && stats->cap < 0) return HGM_E_ARG;
+    const Layout lay = make_layout(gin->n, gin->m, gin->kappa, o);
+    if (!workspace) return HGM_E_ARG;
+    if (ws_bytes < lay.total) return HGM_E_SIZE;
+    if (((uintptr_t)workspace & 255) != 0) return HGM_E_ARG;
+
+    Graph g;
+    memset(&g, 0, sizeof(g));
+    g.n = gin->n;
+    g.m = gin->m;
+    g.kappa = gin->kappa;
+    g.words = ((int64_t)gin->m + 31) / 32;
+    g.pairs = o.pairs ? 1 : 0;
+    g.e_off = o.pairs ? nullptr : gin->e_off;
+    g.e_pins = gin->e_pins;
+    g.v_off = gin->v_off;
+    g.v_edges = gin->v_edges;
+    g.w = gin->w;
+    const State s = carve(workspace, lay, o);
+    Launch L;
+    L.grid = device_grid();
+    L.stream = (hipStream_t)stream;
+    if (L.grid <= 0) return HGM_E_HIP;
+    return run_rounds(g, o, lay, s, L, seed, matched_bits, stats, nullptr);
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,37 +624,27 @@ size_t hgm_workspace_size(const hgm_csr *g, const hgm_opts *opts) {
 
 int hgm_match(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *workspace,
               size_t ws_bytes, const hgm_opts *opts, void *stream, hgm_stats *stats) {
-    Opts o;
-    int rc = resolve_opts(opts, &o);
-    if (rc != HGM_OK) return rc;
-    rc = check_graph(gin, o);
-    if (rc != HGM_OK) return rc;
-    bind_graph(&o, gin);
-    if (gin->m > 0 && !matched_bits) return HGM_E_ARG;
-    if (stats && stats->cap < 0) return HGM_E_ARG;
-    const Layout lay = make_layout(gin->n, gin->m, gin->kappa, o);
-    if (!workspace) return HGM_E_ARG;
-    if (ws_bytes < lay.total) return HGM_E_SIZE;
-    if (((uintptr_t)workspace & 255) != 0) return HGM_E_ARG;
+    return match_one(gin, seed, matched_bits, workspace, ws_bytes, opts, stream, stats);
+}
 
-    Graph g;
-    memset(&g, 0, sizeof(g));
-    g.n = gin->n;
-    g.m = gin->m;
-    g.kappa = gin->kappa;
-    g.words = ((int64_t)gin->m + 31) / 32;
-    g.pairs = o.pairs ? 1 : 0;
-    g.e_off = o.pairs ? nullptr : gin->e_off;
-    g.e_pins = gin->e_pins;
-    g.v_off = gin->v_off;
-    g.v_edges = gin->v_edges;
-    g.w = gin->w;
-    const State s = carve(workspace, lay, o);
-    Launch L;
-    L.grid = device_grid();
-    L.stream = (hipStream_t)stream;
-    if (L.grid <= 0) return HGM_E_HIP;
-    return run_rounds(g, o, lay, s, L, seed, matched_bits, stats, nullptr);
+size_t hgm_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int hgm_match_noalloc(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits,
+                      const hgm_opts *opts, void *stream, hgm_stats *stats) {
+    // Per-kernel timing creates HIP events, which this entry point avoids.
+    if (stats && stats->timing) return HGM_E_ARG;
+    const size_t need = hgm_workspace_size(gin, opts);
+    if (need == 0) {  // invalid sizes or options: the checks of hgm_match report which
+        Opts o;
+        int rc = resolve_opts(opts, &o);
+        if (rc != HGM_OK) return rc;
+        rc = check_graph(gin, o);
+        return rc != HGM_OK ? rc : HGM_E_ARG;
+    }
+    if (need > kScratchBytes) return HGM_E_SIZE;
+    void *ws = scratch_address();
+    if (!ws) return HGM_E_HIP;
+    return match_one(gin, seed, matched_bits, ws, kScratchBytes, opts, stream, stats);
 }
 
 size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts) {

@@ -116,6 +116,26 @@ def test_match_rejects_bad_arguments_without_gpu(lib):
     assert hgm.hgm_match(_csr(5, 5, 10), 1, bits, ws, 1 << 30, bad) == hgm.HGM_E_ARG
 
 
+def test_noalloc_arguments_without_gpu(lib):
+    """hgm_match_noalloc refuses before any HIP call: bad sizes and options
+    as hgm_match does, a workspace beyond its fixed array (HGM_E_SIZE) and
+    timing statistics (HGM_E_ARG)."""
+    bits = 0x2000
+    cap = hgm.hgm_noalloc_max_bytes()
+    assert cap == 64 << 20
+    assert hgm.hgm_match_noalloc(_csr(-1, 5, 5), 1, bits) == hgm.HGM_E_ARG
+    assert hgm.hgm_match_noalloc(_csr(5, 5, 2 ** 31), 1, bits) == hgm.HGM_E_SIZE
+    assert hgm.hgm_match_noalloc(_csr(5, 5, 5), 1, bits,
+                                 hgm.make_opts(variant=9)) == hgm.HGM_E_ARG
+    assert lib.hgm_match_noalloc(None, 1, None, None, None, None) == hgm.HGM_E_ARG
+    big = _csr(2_000_000, 5_000_000, 30_000_000)
+    assert hgm.hgm_workspace_size(big) > cap
+    assert hgm.hgm_match_noalloc(big, 1, bits) == hgm.HGM_E_SIZE
+    st = hgm.HgmStats()
+    st.timing = 1
+    assert hgm.hgm_match_noalloc(_csr(5, 5, 5), 1, bits, None, 0, st) == hgm.HGM_E_ARG
+
+
 def test_product_package_does_not_use_the_oracle():
     pkg = os.path.join(ROOT, "paper_2602_22976_amd")
     for dirpath, _, files in os.walk(pkg):
