@@ -98,8 +98,10 @@ typedef struct hgm_opts {
                                 first (the per-round random weights of
                                 Algorithm 1, first phase).  The result is then
                                 a maximal matching but in general not the
-                                greedy one.  Not with HGM_VARIANT_CREW nor with
-                                hgm_match_batch (HGM_E_ARG). */
+                                greedy one, and still exactly one bitmap per
+                                (instance, seed).  Every variant; in
+                                hgm_match_batch instance i uses
+                                H(H(seed_i, r), local id). */
     int32_t pairs;           /* 1: a graph (every edge has exactly two pins,
                                 Section 6.3): the pins of edge e are
                                 e_pins[2e] and e_pins[2e + 1], e_off is not

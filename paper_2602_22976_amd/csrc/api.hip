@@ -34,7 +34,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
-    size_t key, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
+    size_t key, eseed, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
         piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, total;
     int ring, grid, region, piece_cap;
@@ -65,8 +65,6 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     if (d.hub_threshold < 0 || d.rounds_per_sync < 0 || d.max_rounds < 0) return HGM_E_ARG;
     if (d.rounds_per_sync > kMaxRoundsPerSync) return HGM_E_ARG;
     if (d.reseed != 0 && d.reseed != 1) return HGM_E_ARG;
-    // The CREW rounds gather a live key stored once for the whole run.
-    if (d.reseed && d.variant == HGM_VARIANT_CREW) return HGM_E_ARG;
     if (d.pairs != 0 && d.pairs != 1) return HGM_E_ARG;
     // The pair layout has no edge offsets for the CREW rounds' edge-side passes
     // to share; graphs run the edge-centric rounds.
@@ -108,6 +106,7 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     const size_t cap = (size_t)L.grid * (size_t)L.region;
     L.stored_keys = batch;
     L.key = take(batch ? 8 * (size_t)m : 0);
+    L.eseed = take(batch && o.reseed ? 8 * (size_t)m : 0);
     L.best0 = take(8 * (size_t)n);
     L.best1 = take(8 * (size_t)n);
     L.done = take((size_t)n);
@@ -155,6 +154,7 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     char *b = (char *)ws;
     State s;
     s.key = L.stored_keys ? (uint64_t *)(b + L.key) : nullptr;
+    s.eseed = L.stored_keys && o.reseed ? (uint64_t *)(b + L.eseed) : nullptr;
     s.best[0] = (uint64_t *)(b + L.best0);
     s.best[1] = (uint64_t *)(b + L.best1);
     s.done = (uint8_t *)(b + L.done);
@@ -240,7 +240,6 @@ int check_batch(const hgm_batch *b, const Opts &o) {
         if (b->kappa_total > 0 && (!b->v_edges || b->n_total == 0)) return HGM_E_ARG;
     }
     if (o.validate) return HGM_E_ARG;  // validate each instance with hgm_match instead
-    if (o.reseed) return HGM_E_ARG;    // per-round seeds are defined for one instance
     if (o.pairs) return HGM_E_ARG;     // batches use the offset layout
     return HGM_OK;
 }
@@ -375,7 +374,7 @@ struct KernelTimer {
 int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s, const Launch &L,
                uint32_t seed, uint32_t *matched_bits, hgm_stats *stats, const BatchIn *batch) {
     int init_flags = 0;
-    if (uses_live_key(o)) init_flags |= kInitLiveKey;
+    if (uses_live_key(o)) init_flags |= kInitLiveKey | (o.reseed ? kInitLiveMark : 0);
     // Priority seed of round r.
     auto kseed = [&](int r) { return o.reseed ? round_seed(seed, r) : seed; };
     if (any_crew_round(o)) init_flags |= kInitHubs;
@@ -425,7 +424,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             max0_event = (int)T.cls.size();
             HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
         } else if (crew_round(o, 0)) {
-            HGM_TRY(launch_vertex_max(L, g, s, 0, kseed(0)));
+            HGM_TRY(launch_vertex_max(L, g, s, 0, kseed(0), 0));
             HGM_TRY(T.after(HGM_K_VERTEX_MAX, 0));
         } else {
             HGM_TRY(launch_scatter(L, g, s, kseed(0)));
@@ -465,7 +464,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1), o.reseed ? 1 : 0));
             HGM_TRY(T.after(HGM_K_RETIRE, r));
             if (next_crew) {
-                HGM_TRY(launch_vertex_max(L, g, s, r + 1, seed));
+                HGM_TRY(launch_vertex_max(L, g, s, r + 1, kseed(r + 1), o.reseed ? 1 : 0));
                 HGM_TRY(T.after(HGM_K_VERTEX_MAX, r + 1));
             }
             launched += 1;
@@ -680,6 +679,7 @@ int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace,
     in.e_off = b->e_off;
     in.v_off = o.have_vertex_side ? b->v_off : nullptr;
     in.seeds = b->seeds;
+    in.reseed = o.reseed ? 1 : 0;
     in.goff = (int32_t *)(base + lay.goff);
     in.vbase = (int32_t *)(base + lay.vbase);
     in.bitoff = (int32_t *)(base + lay.bitoff);

@@ -81,6 +81,8 @@ struct BatchIn {
     const int32_t *e_off;     // [m_total + count] local offsets, instance i at e_base[i] + i
     const int32_t *v_off;     // [n_total + count] local offsets, instance i at v_base[i] + i
     const uint32_t *seeds;    // [count]
+    int32_t reseed;           // priorities redrawn every round: keys of round 0 use
+                              // H(seed_i, 0) and eseed keeps seed_i and the local id
     int32_t *goff;            // out [m_total + 1]
     int32_t *vbase;           // out [m_total]
     int32_t *bitoff;          // out [m_total]
@@ -99,6 +101,8 @@ struct BatchIn {
 struct State {
     uint64_t *key;      // [m] batch only: packed key w<<32 | H(seed_i, local id); NULL for
                         // one instance, whose keys are rebuilt from w and the round's seed
+    uint64_t *eseed;    // [m] batch with priorities redrawn every round: seed_i << 32 |
+                        // local id, from which round r's key is rebuilt (NULL otherwise)
     uint64_t *best[2];  // [n] per-vertex maximum live key, double-buffered by round parity
     uint8_t *done;      // [n] vertex is a pin of a matched edge
     int32_t *list[2];   // [grid * region] live edges per workgroup region
@@ -117,7 +121,9 @@ struct State {
     int32_t region;     // edge ids (and list capacity) per workgroup, multiple of kBlock
     int32_t *err;       // [1] validation error flag
     // Vertex-centric (CREW) extras
-    uint64_t *live_key; // [m] key while live, 0 once matched or retired (CREW variant)
+    uint64_t *live_key; // [m] key while live, 0 once matched or retired (CREW variant);
+                        // with priorities redrawn every round w << 32 | 1 while live
+                        // (a liveness mark that keeps the weight)
     int2 *pieces;       // [piece_cap] (hub vertex, piece index): the incidence list of a
                         // vertex of degree > hub threshold is cut into kHubPiece pieces
     int32_t *piece_count;  // [1]
@@ -144,6 +150,8 @@ constexpr int kInitLiveKey = 1;  // copy keys to live_key (CREW variant)
 constexpr int kInitHubs = 2;     // cut high-degree vertices into pieces (any CREW round)
 constexpr int kInitWeightRange = 4;  // smallest and largest weight (CREW round-0 vertex pass,
                                      // one instance: equal weights need no gather)
+constexpr int kInitLiveMark = 8;     // with kInitLiveKey: live_key = w << 32 | 1 (priorities
+                                     // redrawn every round)
 // `kseed` arguments: the priority seed of the round the kernel works on
 // (the call's seed, or round_seed(seed, r) when the order is redrawn);
 // `rekey`: nonzero when the order is redrawn every round.
@@ -155,7 +163,7 @@ hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint3
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
                          uint32_t kseed, int rekey);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
-                             uint32_t seed);
+                             uint32_t kseed, int rekey);
 // Round-0 maximum in the form chosen from the degree profile (AUTO): two
 // launches, of which the one not chosen returns at once.
 hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t seed);

@@ -46,6 +46,22 @@ __device__ __forceinline__ uint64_t edge_key(const Graph &g, const State &s, uin
     return ((uint64_t)g.w[e] << 32) | priority_hash(kseed, (uint32_t)e);
 }
 
+// Key of edge e in round `round` when priorities are redrawn every round.
+// One instance: kseed is the round's seed H(seed, round), derived on the
+// host.  A batch: each instance has its own seed, so the round seed
+// H(seed_i, round) is derived per edge from the seed and local id that the
+// batch setup kept.
+template <bool kB>
+__device__ __forceinline__ uint64_t round_key(const Graph &g, const State &s, uint32_t kseed,
+                                              int round, int e) {
+    if constexpr (kB) {
+        const uint64_t sl = s.eseed[e];
+        const uint32_t rs = round_seed((uint32_t)(sl >> 32), round);
+        return ((uint64_t)g.w[e] << 32) | priority_hash(rs, (uint32_t)sl);
+    }
+    return edge_key<false>(g, s, kseed, e);
+}
+
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
@@ -314,8 +330,9 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
         if (i < g.m && (flags & kInitLiveKey))
-            s.live_key[i] = s.key ? edge_key<true>(g, s, seed, (int)i)
-                                  : edge_key<false>(g, s, seed, (int)i);
+            s.live_key[i] = (flags & kInitLiveMark) ? ((uint64_t)g.w[i] << 32) | 1u
+                            : s.key                 ? edge_key<true>(g, s, seed, (int)i)
+                                                    : edge_key<false>(g, s, seed, (int)i);
         if (i < g.n) {
             s.best[0][i] = 0;
             s.done[i] = 0;
@@ -413,9 +430,10 @@ struct EdgeRec {
     uint64_t key;
 };
 
+// key_round: the round whose key a rekeying caller needs.
 template <bool kB>
 __device__ __forceinline__ EdgeRec edge_rec(const Graph &g, const State &s, int round, int b,
-                                            int i, uint32_t kseed, bool rekey) {
+                                            int i, uint32_t kseed, bool rekey, int key_round) {
     EdgeRec r;
     const int64_t at = (int64_t)b * s.region + i;
     if (round == 0) {
@@ -423,7 +441,7 @@ __device__ __forceinline__ EdgeRec edge_rec(const Graph &g, const State &s, int 
         r.base = g.e_off[r.e];
         r.len = g.e_off[r.e + 1] - r.base;
         r.vb = kB ? g.vbase[r.e] : 0;
-        r.key = edge_key<kB>(g, s, kseed, r.e);
+        r.key = rekey ? round_key<kB>(g, s, kseed, key_round, r.e) : edge_key<kB>(g, s, kseed, r.e);
         r.pin0 = r.len > 0 ? g.e_pins[r.base] + r.vb : -1;
     } else {
         const int k = round & 1;
@@ -432,7 +450,7 @@ __device__ __forceinline__ EdgeRec edge_rec(const Graph &g, const State &s, int 
         r.len = s.rec_b[k][at];
         r.pin0 = s.rec_c[k][at];
         r.vb = kB ? s.rec_vb[k][at] : 0;
-        r.key = rekey ? edge_key<kB>(g, s, kseed, r.e) : s.rec_key[k][at];
+        r.key = rekey ? round_key<kB>(g, s, kseed, key_round, r.e) : s.rec_key[k][at];
     }
     return r;
 }
@@ -446,12 +464,12 @@ __device__ __forceinline__ void pair_rec(const Graph &g, const State &s, int rou
     if (round == 0) {
         e = (int)at;
         p = pair_pins(g, e);
-        key = edge_key<kB>(g, s, kseed, e);
+        key = rekey ? round_key<kB>(g, s, kseed, round + 1, e) : edge_key<kB>(g, s, kseed, e);
     } else {
         const int k = round & 1;
         e = s.list[k][at];
         p = make_int2(s.rec_a[k][at], s.rec_b[k][at]);
-        key = rekey ? edge_key<kB>(g, s, kseed, e) : s.rec_key[k][at];
+        key = rekey ? round_key<kB>(g, s, kseed, round + 1, e) : s.rec_key[k][at];
     }
 }
 
@@ -589,7 +607,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         uint64_t key = 0;
         int vb = 0;
         if (i < cnt) {
-            const EdgeRec r = edge_rec<kB>(g, s, round - 1, b, i, kseed, rekey != 0);
+            const EdgeRec r = edge_rec<kB>(g, s, round - 1, b, i, kseed, rekey != 0, round);
             e = r.e;
             base = r.base;
             len = r.len;
@@ -720,21 +738,29 @@ __device__ __forceinline__ void weight_range(const State &s, uint32_t *wlo, bool
     *uniform = lo == hi;
 }
 
-// uniform_w: every weight equals wlo (one instance, round 0), so the key
-// needs no gather.
+// Key of incident edge e in the vertex pass of round r, and whether e is
+// live.  uniform_w: every weight equals wlo (one instance, round 0), so the
+// key needs no gather.  From round 1 on live_key says whether e is live; it
+// holds the key itself, or with rekey (priorities redrawn every round) a
+// liveness mark with the weight, and the key is rebuilt for the round.  A
+// live edge whose key is 0 is kept in the lists: with rekey its key changes.
 template <bool kB>
 __device__ __forceinline__ uint64_t vertex_key(const Graph &g, const State &s, int round,
                                                uint32_t seed, int e, bool uniform_w,
-                                               uint32_t wlo) {
+                                               uint32_t wlo, bool rekey, bool *live) {
+    *live = true;
     if (!kB && round == 0 && uniform_w)
         return ((uint64_t)wlo << 32) | priority_hash(seed, (uint32_t)e);
-    return round == 0 ? edge_key<kB>(g, s, seed, e) : s.live_key[e];
+    if (round == 0) return edge_key<kB>(g, s, seed, e);
+    const uint64_t lk = s.live_key[e];
+    *live = lk != 0;
+    return (rekey && lk) ? round_key<kB>(g, s, seed, round, e) : lk;
 }
 
 // kCompact: rounds >= 1 (list compaction); round 0 instantiates without it.
 template <bool kCompact, bool kB>
 __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, ChunkLds &L,
-                                                int round, uint32_t seed) {
+                                                int round, uint32_t seed, bool rekey) {
     uint64_t *best = s.best[round & 1];
     const int lane = threadIdx.x & (kWave - 1);
     const int hub_threshold = s.hub_threshold;
@@ -768,13 +794,13 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             const int i = i0 + threadIdx.x;
             int e = -1;
             uint64_t k = 0;
+            bool live = false;
             if (i < p1) {
                 e = src[vo + i] + eb;
-                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo);
+                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo, rekey, &live);
             }
             mx = k > mx ? k : mx;
             if constexpr (compact) {
-                const bool live = k != 0;
                 const unsigned long long mask = __ballot(live);
                 const int cnt = __popcll(mask);
                 int at = 0;
@@ -816,9 +842,10 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
             if (t < total) {
                 j = find_item(L.start, t);
                 const int e = src[L.base[j] + (t - L.start[j])] + (kB ? L.vb[j] : 0);
-                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo);
+                bool live;
+                k = vertex_key<kB>(g, s, round, seed, e, uniform_w, wlo, rekey, &live);
                 if constexpr (compact) {
-                    if (k != 0) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
+                    if (live) dst[L.base[j] + atomicAdd(&L.flag[j], 1)] = e;
                 }
             }
             // segmented inclusive max-scan over the wave, segments = equal j
@@ -841,13 +868,16 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
     }
 }
 
+// seed: the round's priority seed (one instance); rekey: priorities are
+// redrawn every round, so keys are rebuilt instead of read from live_key.
 template <bool kB>
-__global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, uint32_t seed) {
+__global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int round, uint32_t seed,
+                                                       int rekey) {
     __shared__ ChunkLds L;
     if (round == 0)
-        vertex_max_body<false, kB>(g, s, L, round, seed);
+        vertex_max_body<false, kB>(g, s, L, round, seed, false);
     else
-        vertex_max_body<true, kB>(g, s, L, round, seed);
+        vertex_max_body<true, kB>(g, s, L, round, seed, rekey != 0);
 }
 
 // Round-0 maximum when the library chooses the form (AUTO).  The edge-centric
@@ -894,7 +924,7 @@ template <bool kB>
 __global__ void __launch_bounds__(kBlock) k_max0_vertex(Graph g, State s, uint32_t seed) {
     __shared__ ChunkLds L;
     if (max0_edge_form(g, s)) return;
-    vertex_max_body<false, kB>(g, s, L, 0, seed);
+    vertex_max_body<false, kB>(g, s, L, 0, seed, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -985,7 +1015,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
                 pin0[u] = -1;
                 key[u] = 0;
                 if (i < cnt) {
-                    const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false);
+                    const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false, round);
                     e[u] = r.e;
                     base[u] = r.base;
                     len[u] = r.len;
@@ -1023,7 +1053,7 @@ __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, ui
         uint64_t key = 0;
         int vb = 0;
         if (i < cnt) {
-            const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false);
+            const EdgeRec r = edge_rec<kB>(g, s, round, b, i, kseed, false, round);
             e = r.e;
             base = r.base;
             len = r.len;
@@ -1112,7 +1142,10 @@ __global__ void __launch_bounds__(kBlock) k_batch_setup(Graph g, BatchIn b, Stat
             b.goff[e] = (int32_t)(b.pin_base[i] + b.e_off[eb + i + el]);
             b.vbase[e] = (int32_t)b.v_base[i];
             b.bitoff[e] = (int32_t)(32 * b.word_base[i] - eb);
-            s.key[e] = ((uint64_t)g.w[e] << 32) | priority_hash(b.seeds[i], (uint32_t)el);
+            const uint32_t sd = b.seeds[i];
+            s.key[e] = ((uint64_t)g.w[e] << 32) |
+                       priority_hash(b.reseed ? round_seed(sd, 0) : sd, (uint32_t)el);
+            if (b.reseed) s.eseed[e] = ((uint64_t)sd << 32) | (uint32_t)el;
         }
         __syncthreads();  // `first` is reused below
     }
@@ -1214,12 +1247,13 @@ hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t
 }
 
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
-                             uint32_t seed) {
+                             uint32_t kseed, int rekey) {
     const dim3 grid(L.grid), block(kBlock);
     if (g.vbase)
-        hipLaunchKernelGGL(k_vertex_max<true>, grid, block, 0, L.stream, g, s, round, seed);
+        hipLaunchKernelGGL(k_vertex_max<true>, grid, block, 0, L.stream, g, s, round, kseed, rekey);
     else
-        hipLaunchKernelGGL(k_vertex_max<false>, grid, block, 0, L.stream, g, s, round, seed);
+        hipLaunchKernelGGL(k_vertex_max<false>, grid, block, 0, L.stream, g, s, round, kseed,
+                           rekey);
     return hipGetLastError();
 }
 

@@ -71,8 +71,9 @@ def test_workspace_size_layout(lib):
     assert hgm.hgm_workspace_size(_csr(-1, 5, 5)) == 0
     assert hgm.hgm_workspace_size(_csr(5, 5, 2 ** 31)) == 0
     assert hgm.hgm_workspace_size(_csr(5, 5, 5), hgm.make_opts(variant=7)) == 0
-    # per-round priorities need the edge-centric rounds
-    assert hgm.hgm_workspace_size(_csr(5, 5, 5), hgm.make_opts("crew", reseed=True)) == 0
+    # per-round priorities with the vertex-centric rounds: the same layout
+    assert hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000),
+                                  hgm.make_opts("crew", reseed=True)) == crew
     bad = hgm.make_opts()
     bad.reseed = 2
     assert hgm.hgm_workspace_size(_csr(5, 5, 5), bad) == 0
@@ -100,8 +101,6 @@ def test_match_rejects_bad_arguments_without_gpu(lib):
     st.cap = -1
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, None, 0, st) == hgm.HGM_E_ARG
     o = hgm.make_opts(rounds_per_sync=1000)
-    assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
-    o = hgm.make_opts("crew", reseed=True)
     assert hgm.hgm_match(_csr(5, 5, 5), 1, bits, ws, 1 << 30, o) == hgm.HGM_E_ARG
     # pairs (graphs): kappa must be 2m, e_pins 8-byte aligned, e_off optional
     assert hgm.hgm_match(_csr(5, 5, 9), 1, bits, ws, 1 << 30,
@@ -169,8 +168,8 @@ def test_batch_arguments_without_gpu(lib):
     assert hgm.hgm_match_batch(ok, bits, ws, 64) == hgm.HGM_E_SIZE
     assert hgm.hgm_match_batch(ok, 0, ws, 1 << 30) == hgm.HGM_E_ARG
     assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(validate=True)) == hgm.HGM_E_ARG
-    assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(reseed=True)) == hgm.HGM_E_ARG
-    assert hgm.hgm_batch_workspace_size(ok, hgm.make_opts(reseed=True)) == 0
+    # per-round priorities: each edge also keeps its instance's seed and local id
+    assert hgm.hgm_batch_workspace_size(ok, hgm.make_opts(reseed=True)) >= size + 8 * 200 - 256
     assert hgm.hgm_match_batch(ok, bits, ws, 1 << 30, hgm.make_opts(pairs=True)) == hgm.HGM_E_ARG
     b = _batch(4, 100, 200, 800, 8)
     b.seeds = None

@@ -67,7 +67,7 @@ def test_shuffled_lists_fixed_order(hgm, shuffled, name, variant):
 
 
 @pytest.mark.parametrize("name", ["random", "hub", "power-law"])
-@pytest.mark.parametrize("variant", ["auto", "crcw"])
+@pytest.mark.parametrize("variant", ["auto", "crcw", "crew"])
 def test_shuffled_lists_reseed(hgm, shuffled, name, variant):
     g, s = shuffled[name]
     seed = 9

@@ -15,7 +15,7 @@ from tests.fixtures import disjoint, path_graph, star
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = ["crcw", "auto"]
+VARIANTS = ["crcw", "auto", "crew"]
 
 
 @pytest.fixture(scope="module")
@@ -124,8 +124,88 @@ def test_reseed_differs_from_fixed_order(hgm):
     assert np.array_equal(b.cpu().numpy().view(np.uint32), resd)
 
 
-def test_power_law_full_reseed(hgm):
+@pytest.fixture(scope="module")
+def power_law():
+    return synth.config_power_law()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_power_law_full_reseed(hgm, power_law, variant):
     """The large power-law workload (n = 2M, m = 5M) at full size."""
-    g = synth.config_power_law()
-    print(f"reseed power-law n={g.n} m={g.m} kappa={g.kappa}", flush=True)
-    _check(hgm, g, 1, "auto")
+    g = power_law
+    print(f"reseed power-law n={g.n} m={g.m} kappa={g.kappa} variant={variant}", flush=True)
+    _check(hgm, g, 1, variant)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_hub_stress_full_reseed(hgm, variant):
+    """The hub-stress workload (n = 1M, m = 4M, all weights 1, one vertex in
+    a quarter of the edges) at full size: the order is the per-round hash
+    alone, and the hub is split into pieces in the vertex-centric rounds."""
+    g = synth.config_hub_stress()
+    print(f"reseed hub-stress n={g.n} m={g.m} kappa={g.kappa} variant={variant}", flush=True)
+    _check(hgm, g, 1, variant)
+
+
+def _batch_reseed_check(hgm, b, variant, **kw):
+    """Every instance of a reseeded batch equals the oracle's reseeded round
+    simulator with the instance's own seed, and hgm_match on the instance
+    alone with that seed."""
+    import torch
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    bits, st = hgm.match_batch(db, hgm.make_opts(variant, reseed=True, **kw))
+    torch.cuda.synchronize()
+    got = bits.cpu().numpy().view(np.uint32)
+    R = 0
+    live_pins = {}
+    for i in range(b.count):
+        g = b.instance(i)
+        seed = int(b.seeds[i])
+        exp, ref = oracle.local_max(g.n, g.m, g.e_off, g.e_pins, g.v_off, g.v_edges, g.w, seed,
+                                    reseed=True)
+        seg = got[int(b.word_base[i]):int(b.word_base[i + 1])]
+        assert np.array_equal(seg, exp), f"instance {i} (seed {seed}, m={g.m}) differs"
+        for r, p in enumerate(ref["live_pins"]):
+            live_pins[r] = live_pins.get(r, 0) + int(p)
+        R = max(R, ref["rounds"])
+    assert st["rounds"] == R
+    assert np.array_equal(st["live_pins"], np.array([live_pins[r] for r in range(R)]))
+    return got
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_batch_reseed(hgm, variant):
+    """A batch of uneven instances (some with equal weights, so the per-round
+    hash decides, one empty) with per-round priorities."""
+    graphs, seeds = [], []
+    for i in range(40):
+        n = int(np.exp(np.random.default_rng(i).uniform(np.log(5), np.log(4000))))
+        wmax = 1 if i % 3 == 0 else 1000
+        graphs.append(synth.random_instance(700 + i, n, 2 * n, 2, 8, 1, wmax))
+        seeds.append((i * 2654435761) & 0xFFFFFFFF)
+    graphs.append(synth.from_edge_lists(3, [], []))
+    seeds.append(5)
+    b = synth.batch_from_instances(graphs, seeds)
+    print(f"reseed batch count={b.count} variant={variant}", flush=True)
+    got = _batch_reseed_check(hgm, b, variant)
+    # the same instances alone give the same bitmaps
+    import torch
+    for i in (0, 1, 7, 39):
+        g = b.instance(i)
+        dg = hgm.DeviceHypergraph.from_host(g, "cuda:0")
+        alone, _ = hgm.match(dg, int(b.seeds[i]), hgm.make_opts(variant, reseed=True))
+        torch.cuda.synchronize()
+        seg = got[int(b.word_base[i]):int(b.word_base[i + 1])]
+        assert np.array_equal(alone.cpu().numpy().view(np.uint32), seg)
+
+
+def test_batch_reseed_path_rounds(hgm):
+    """Paths with increasing weights in a batch take many rounds (the path of
+    201 edges 101): round seeds must follow the round index in every
+    instance, through several host synchronisations."""
+    graphs = [path_graph(201), path_graph(40), star(500, seed=3)]
+    for g in graphs[:2]:
+        g.w[:] = 1 + (np.arange(g.m) % 3)
+    b = synth.batch_from_instances(graphs, [3, 4, 5])
+    for variant in VARIANTS:
+        _batch_reseed_check(hgm, b, variant, rounds_per_sync=3)
