@@ -110,6 +110,32 @@ typedef struct hgm_opts {
                                 edge is then handled by one lane with one
                                 8-byte pin load.  Not with HGM_VARIANT_CREW
                                 nor with hgm_match_batch (HGM_E_ARG). */
+    int32_t solo_max_kappa;  /* hgm_match_batch: instances with at most this
+                                many pins (and at most 8 LDS tiles of
+                                vertices, see hgm_solo_lds_vertices) are
+                                matched whole by one workgroup each, every
+                                round inside it, with their per-vertex state
+                                in LDS; the others go through the round
+                                kernels together.  0 = library default
+                                (2^20), -1 = none. */
+    /* Schedule (any value gives the same result; hgm_tune picks them per
+     * shape).  0 = library default for each. */
+    int32_t edge_grid;       /* workgroups of the edge-centric kernels, each
+                                owning a fixed range of edge ids (default
+                                2048, at most 65536) */
+    int32_t blocks_per_cu;   /* workgroups per compute unit of the vertex-
+                                centric and setup kernels (default 8, at
+                                most 32) */
+    int32_t clear_ratio;     /* the test clears the next round's maximum by
+                                one streaming pass when the round has at
+                                least n / clear_ratio live pins, else at each
+                                pin it visits (default 8) */
+    int32_t hot_degree;      /* AUTO's round 0 is edge-centric when at least
+                                half the pins lie on vertices of at least
+                                this degree (default 64) */
+    int32_t first_batch_pct; /* rounds enqueued before the first termination
+                                check: pct / 100 * log2(kappa) (default 40,
+                                35 for graphs; at most 400) */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */
@@ -118,7 +144,8 @@ typedef struct hgm_opts {
 #define HGM_K_VERTEX_MAX 2 /* vertex-centric maximum (CREW) */
 #define HGM_K_TEST 3       /* local-max test and marking */
 #define HGM_K_RETIRE 4     /* retire + live-list compaction (+ next maximum in CRCW) */
-#define HGM_K_CLASSES 5
+#define HGM_K_SOLO 5       /* batches: every round of the instances matched by one workgroup */
+#define HGM_K_CLASSES 6
 
 /* Optional statistics (host memory).  The arrays may be NULL; when given they
  * hold `cap` entries and receive, for round r < cap: the number of live edges
@@ -217,6 +244,12 @@ typedef struct hgm_batch {
     const uint32_t *seeds;
 } hgm_batch;
 
+/* Vertices of one LDS tile of the one-workgroup path on the current device:
+ * an instance of a batch with at most this many vertices forms each round's
+ * maximum in one pass; one with up to 8 tiles' worth in one pass per tile;
+ * larger ones go through the round kernels. */
+int hgm_solo_lds_vertices(void);
+
 /* Workspace bytes for hgm_match_batch (0 on invalid sizes or options). */
 size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts);
 
@@ -228,6 +261,44 @@ size_t hgm_batch_workspace_size(const hgm_batch *b, const hgm_opts *opts);
  * supported here (HGM_E_ARG): validate instances with hgm_match. */
 int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace, size_t ws_bytes,
                     const hgm_opts *opts, void *stream, hgm_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Schedule autotuner.  The schedule fields of hgm_opts (edge_grid,
+ * blocks_per_cu, hub_threshold, hot_degree, clear_ratio, first_batch_pct,
+ * and solo_max_kappa for batches) change how the work is laid out, never the
+ * result.  hgm_tune times whole matchings of the given instance (median of
+ * `reps` calls after one untimed call) under candidate schedules, by
+ * coordinate descent from `base` (NULL or 0 fields: the defaults), checks
+ * that every candidate produces the starting schedule's bitmap, and returns
+ * the fastest schedule in *best (base's other fields kept).  With a cache
+ * path (or, when `cache` is NULL, the HGM_TUNE_CACHE environment variable)
+ * the result is also stored in that text file under a key of the device
+ * (architecture and compute units) and the shape bucket (kind, variant,
+ * layout, per-round priorities, round(log2 kappa), mean edge size, and for
+ * batches round(log2 count)); hgm_tuned_opts reads it back for an instance
+ * of the same bucket.  The workspace must hold hgm_tune_workspace_size()
+ * bytes (the largest candidate edge grid); matched_bits receives the
+ * matching.  Not part of the paper: a schedule search of this library. */
+typedef struct hgm_tune_report {
+    double ms_default;       /* median time of the starting schedule */
+    double ms_best;          /* median time of the schedule returned */
+    int32_t evaluations;     /* schedules timed */
+    int32_t identical;       /* 1: every candidate gave the starting bitmap */
+} hgm_tune_report;
+
+size_t hgm_tune_workspace_size(const hgm_csr *g, const hgm_opts *base);
+size_t hgm_tune_batch_workspace_size(const hgm_batch *b, const hgm_opts *base);
+int hgm_tune(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits, void *workspace,
+             size_t ws_bytes, const hgm_opts *base, void *stream, int32_t reps,
+             const char *cache, hgm_opts *best, hgm_tune_report *report);
+int hgm_tune_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace, size_t ws_bytes,
+                   const hgm_opts *base, void *stream, int32_t reps, const char *cache,
+                   hgm_opts *best, hgm_tune_report *report);
+/* Looks up the cached schedule for this instance's bucket (variant, pairs
+ * and reseed taken from *opts) and writes its fields into *opts: HGM_OK, or
+ * HGM_E_ARG when there is no cache or no entry (opts unchanged). */
+int hgm_tuned_opts(const char *cache, const hgm_csr *g, hgm_opts *opts);
+int hgm_tuned_batch_opts(const char *cache, const hgm_batch *b, hgm_opts *opts);
 
 /* ---------------------------------------------------------------------------
  * Request server: continuous batching of matching requests on one GPU.

@@ -28,7 +28,14 @@ VARIANTS = {"auto": HGM_VARIANT_AUTO, "crcw": HGM_VARIANT_CRCW, "crew": HGM_VARI
 EXPORTED = ["hgm_workspace_size", "hgm_match", "hgm_batch_workspace_size", "hgm_match_batch",
             "hgm_server_create", "hgm_server_submit", "hgm_server_poll", "hgm_server_info",
             "hgm_server_destroy", "hgm_request_check", "hgm_strerror", "hgm_version",
-            "hgm_source_digest", "hgm_match_noalloc", "hgm_noalloc_max_bytes"]
+            "hgm_source_digest", "hgm_match_noalloc", "hgm_noalloc_max_bytes",
+            "hgm_solo_lds_vertices", "hgm_tune_workspace_size", "hgm_tune_batch_workspace_size",
+            "hgm_tune", "hgm_tune_batch", "hgm_tuned_opts", "hgm_tuned_batch_opts"]
+
+
+class HgmTuneReport(ctypes.Structure):
+    _fields_ = [("ms_default", ctypes.c_double), ("ms_best", ctypes.c_double),
+                ("evaluations", ctypes.c_int32), ("identical", ctypes.c_int32)]
 
 
 class HgmCsr(ctypes.Structure):
@@ -42,7 +49,13 @@ class HgmOpts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("hub_threshold", ctypes.c_int32),
                 ("rounds_per_sync", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("reseed", ctypes.c_int32),
-                ("pairs", ctypes.c_int32)]
+                ("pairs", ctypes.c_int32), ("solo_max_kappa", ctypes.c_int32),
+                ("edge_grid", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("clear_ratio", ctypes.c_int32), ("hot_degree", ctypes.c_int32),
+                ("first_batch_pct", ctypes.c_int32)]
+
+SCHEDULE_FIELDS = ["hub_threshold", "solo_max_kappa", "edge_grid", "blocks_per_cu",
+                   "clear_ratio", "hot_degree", "first_batch_pct"]
 
 
 class HgmBatch(ctypes.Structure):
@@ -79,9 +92,9 @@ class HgmServerState(ctypes.Structure):
                 ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
 
 
-HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE = range(5)
-HGM_K_CLASSES = 5
-KERNEL_CLASS_NAMES = ["setup", "scatter", "vertex_max", "test", "retire"]
+HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE, HGM_K_SOLO = range(6)
+HGM_K_CLASSES = 6
+KERNEL_CLASS_NAMES = ["setup", "scatter", "vertex_max", "test", "retire", "solo"]
 
 
 class HgmStats(ctypes.Structure):
@@ -131,6 +144,27 @@ def load():
                                       ctypes.POINTER(HgmOpts), P, ctypes.POINTER(HgmStats)]
     lib.hgm_noalloc_max_bytes.restype = ctypes.c_size_t
     lib.hgm_noalloc_max_bytes.argtypes = []
+    lib.hgm_tune_workspace_size.restype = ctypes.c_size_t
+    lib.hgm_tune_workspace_size.argtypes = [ctypes.POINTER(HgmCsr), ctypes.POINTER(HgmOpts)]
+    lib.hgm_tune_batch_workspace_size.restype = ctypes.c_size_t
+    lib.hgm_tune_batch_workspace_size.argtypes = [ctypes.POINTER(HgmBatch),
+                                                  ctypes.POINTER(HgmOpts)]
+    lib.hgm_tune.restype = ctypes.c_int
+    lib.hgm_tune.argtypes = [ctypes.POINTER(HgmCsr), ctypes.c_uint32, P, P, ctypes.c_size_t,
+                             ctypes.POINTER(HgmOpts), P, ctypes.c_int32, ctypes.c_char_p,
+                             ctypes.POINTER(HgmOpts), ctypes.POINTER(HgmTuneReport)]
+    lib.hgm_tune_batch.restype = ctypes.c_int
+    lib.hgm_tune_batch.argtypes = [ctypes.POINTER(HgmBatch), P, P, ctypes.c_size_t,
+                                   ctypes.POINTER(HgmOpts), P, ctypes.c_int32, ctypes.c_char_p,
+                                   ctypes.POINTER(HgmOpts), ctypes.POINTER(HgmTuneReport)]
+    lib.hgm_tuned_opts.restype = ctypes.c_int
+    lib.hgm_tuned_opts.argtypes = [ctypes.c_char_p, ctypes.POINTER(HgmCsr),
+                                   ctypes.POINTER(HgmOpts)]
+    lib.hgm_tuned_batch_opts.restype = ctypes.c_int
+    lib.hgm_tuned_batch_opts.argtypes = [ctypes.c_char_p, ctypes.POINTER(HgmBatch),
+                                         ctypes.POINTER(HgmOpts)]
+    lib.hgm_solo_lds_vertices.restype = ctypes.c_int
+    lib.hgm_solo_lds_vertices.argtypes = []
     lib.hgm_batch_workspace_size.restype = ctypes.c_size_t
     lib.hgm_batch_workspace_size.argtypes = [ctypes.POINTER(HgmBatch), ctypes.POINTER(HgmOpts)]
     lib.hgm_match_batch.restype = ctypes.c_int
@@ -293,7 +327,8 @@ class DeviceBatch:
 
 
 def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False,
-              max_rounds=0, reseed=False, pairs=False) -> HgmOpts:
+              max_rounds=0, reseed=False, pairs=False, solo_max_kappa=0, edge_grid=0,
+              blocks_per_cu=0, clear_ratio=0, hot_degree=0, first_batch_pct=0) -> HgmOpts:
     o = HgmOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.hub_threshold = hub_threshold
@@ -302,6 +337,9 @@ def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False
     o.max_rounds = max_rounds
     o.reseed = 1 if reseed else 0
     o.pairs = 1 if pairs else 0
+    o.solo_max_kappa = solo_max_kappa
+    o.edge_grid, o.blocks_per_cu, o.clear_ratio = edge_grid, blocks_per_cu, clear_ratio
+    o.hot_degree, o.first_batch_pct = hot_degree, first_batch_pct
     return o
 
 
@@ -391,6 +429,77 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
     if rc != HGM_OK:
         raise HgmError(rc, "hgm_match")
     return bits[:words], (_stats_dict(st, arrays, rms, timing) if st is not None else None)
+
+
+def opts_dict(o: HgmOpts) -> dict:
+    return {f: int(getattr(o, f)) for f in SCHEDULE_FIELDS}
+
+
+def _enc(path):
+    return path.encode() if isinstance(path, str) else path
+
+
+def tune(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, reps: int = 3,
+         cache: str | None = None, stream=None):
+    """Run hgm_tune on a device hypergraph; returns (best HgmOpts, report dict)."""
+    torch = _torch()
+    dev = dg.e_pins.device
+    c = dg.csr()
+    nbytes = int(load().hgm_tune_workspace_size(ctypes.byref(c),
+                                                ctypes.byref(opts) if opts is not None else None))
+    if nbytes == 0:
+        raise HgmError(HGM_E_ARG, "hgm_tune_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    bits = torch.empty(max((dg.m + 31) // 32, 1), dtype=torch.int32, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    best, rep = HgmOpts(), HgmTuneReport()
+    rc = load().hgm_tune(ctypes.byref(c), seed & 0xFFFFFFFF, bits.data_ptr(), ws.data_ptr(),
+                         nbytes, ctypes.byref(opts) if opts is not None else None, stream or None,
+                         reps, _enc(cache), ctypes.byref(best), ctypes.byref(rep))
+    if rc != HGM_OK:
+        raise HgmError(rc, "hgm_tune")
+    return best, {"ms_default": rep.ms_default, "ms_best": rep.ms_best,
+                  "evaluations": rep.evaluations, "identical": bool(rep.identical),
+                  "opts": opts_dict(best)}
+
+
+def tune_batch(db: DeviceBatch, opts: HgmOpts | None = None, reps: int = 3,
+               cache: str | None = None, stream=None):
+    """Run hgm_tune_batch; returns (best HgmOpts, report dict)."""
+    torch = _torch()
+    dev = db.e_pins.device
+    c = db.c_struct()
+    nbytes = int(load().hgm_tune_batch_workspace_size(
+        ctypes.byref(c), ctypes.byref(opts) if opts is not None else None))
+    if nbytes == 0:
+        raise HgmError(HGM_E_ARG, "hgm_tune_batch_workspace_size")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    bits = torch.empty(max(db.words_total, 1), dtype=torch.int32, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    best, rep = HgmOpts(), HgmTuneReport()
+    rc = load().hgm_tune_batch(ctypes.byref(c), bits.data_ptr(), ws.data_ptr(), nbytes,
+                               ctypes.byref(opts) if opts is not None else None, stream or None,
+                               reps, _enc(cache), ctypes.byref(best), ctypes.byref(rep))
+    if rc != HGM_OK:
+        raise HgmError(rc, "hgm_tune_batch")
+    return best, {"ms_default": rep.ms_default, "ms_best": rep.ms_best,
+                  "evaluations": rep.evaluations, "identical": bool(rep.identical),
+                  "opts": opts_dict(best)}
+
+
+def tuned_opts(dg: DeviceHypergraph, opts: HgmOpts | None = None, cache: str | None = None):
+    """The cached schedule for this instance's bucket, or None."""
+    o = HgmOpts() if opts is None else HgmOpts.from_buffer_copy(opts)
+    rc = load().hgm_tuned_opts(_enc(cache), ctypes.byref(dg.csr()), ctypes.byref(o))
+    return o if rc == HGM_OK else None
+
+
+def tuned_batch_opts(db: DeviceBatch, opts: HgmOpts | None = None, cache: str | None = None):
+    o = HgmOpts() if opts is None else HgmOpts.from_buffer_copy(opts)
+    rc = load().hgm_tuned_batch_opts(_enc(cache), ctypes.byref(db.c_struct()), ctypes.byref(o))
+    return o if rc == HGM_OK else None
 
 
 # ---------------------------------------------------------------------------

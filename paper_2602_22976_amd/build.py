@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhgm.so")
-SOURCES = ["kernels.hip", "api.hip", "server.cpp"]
+SOURCES = ["kernels.hip", "api.hip", "server.cpp", "tune.cpp"]
 
 
 def hipcc() -> str:

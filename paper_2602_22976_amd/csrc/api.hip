@@ -20,15 +20,26 @@ constexpr int kFirstBatch = 4;         // fewest rounds enqueued before the firs
 constexpr int kAdaptiveMaxBatch = 32;  // cap of a predicted batch
 constexpr int kMaxRoundsPerSync = 200;
 constexpr int kDefaultHubThreshold = 8192;
+// Schedule defaults (hgm_opts fields of the same meaning; hgm_tune searches
+// around them).
 constexpr int kBlocksPerCu = 8;
 constexpr int kEdgeGrid = 2048;  // workgroups of the edge kernels (fixed, device independent)
 // The test clears the whole next maximum buffer by streaming when a round has
 // at least n / kFullClearRatio live pins, else at each pin it visits.
 constexpr int kFullClearRatio = 8;
+constexpr int kHotDegree = 64;        // AUTO's round-0 form: degree of a hot vertex
+constexpr int kFirstBatchPct = 40;    // first batch of rounds: 0.40 log2(kappa)
+constexpr int kFirstBatchPctGraph = 35;
 // Per-round shrink of the live pins assumed before two counts are known (the
 // measured ratio on the synthetic workloads lies between 0.2 and 0.35 in the
 // early rounds).
 constexpr double kPriorShrink = 0.3;
+// Batches: instances with at most this many pins are matched whole by one
+// workgroup (k_solo) unless the options say otherwise.
+constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
+// Rounds of per-round sums the solo part records (later rounds of a solo
+// instance count in the totals only).
+constexpr int kSoloRounds = 1 << 16;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -36,21 +47,23 @@ struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
     size_t key, eseed, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
-        piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, total;
-    int ring, grid, region, piece_cap;
+        piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, solo, total;
+    int ring, grid, region, piece_cap, solo_rounds;
 };
 
 // Edge schedule: `grid` workgroups, each owning `region` consecutive edge ids
 // (a multiple of kBlock); grid * region >= m.
-void edge_schedule(int64_t m, int *grid, int *region) {
+void edge_schedule(int64_t m, int edge_grid, int *grid, int *region) {
     const int64_t chunks = std::max<int64_t>(1, (m + kBlock - 1) / kBlock);
-    const int64_t g = std::min<int64_t>(kEdgeGrid, chunks);
+    const int64_t g = std::min<int64_t>(edge_grid, chunks);
     *grid = (int)g;
     *region = (int)(((chunks + g - 1) / g) * kBlock);
 }
 
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
+    int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part)
+    int edge_grid, blocks_per_cu, clear_ratio, hot_degree, first_batch_pct;  // 0 = per kind
     bool reseed;            // priorities redrawn every round (round_seed)
     bool pairs;             // graph: two pins per edge at e_pins[2e], no offsets
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
@@ -77,6 +90,17 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     o->max_rounds = d.max_rounds;
     o->reseed = d.reseed != 0;
     o->pairs = d.pairs != 0;
+    if (d.solo_max_kappa < -1) return HGM_E_ARG;
+    o->solo_max_kappa = d.solo_max_kappa == 0 ? kDefaultSoloMaxKappa : d.solo_max_kappa;
+    if (d.edge_grid < 0 || d.edge_grid > 65536 || d.blocks_per_cu < 0 || d.blocks_per_cu > 32 ||
+        d.clear_ratio < 0 || d.clear_ratio > (1 << 20) || d.hot_degree < 0 ||
+        d.first_batch_pct < 0 || d.first_batch_pct > 400)
+        return HGM_E_ARG;
+    o->edge_grid = d.edge_grid ? d.edge_grid : kEdgeGrid;
+    o->blocks_per_cu = d.blocks_per_cu ? d.blocks_per_cu : kBlocksPerCu;
+    o->clear_ratio = d.clear_ratio ? d.clear_ratio : kFullClearRatio;
+    o->hot_degree = d.hot_degree ? d.hot_degree : kHotDegree;
+    o->first_batch_pct = d.first_batch_pct;  // 0: resolved per instance (graphs differ)
     return HGM_OK;
 }
 
@@ -102,7 +126,7 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
         return p;
     };
     L.ring = o.rounds_per_sync + 2;
-    edge_schedule(m, &L.grid, &L.region);
+    edge_schedule(m, o.edge_grid, &L.grid, &L.region);
     const size_t cap = (size_t)L.grid * (size_t)L.region;
     L.stored_keys = batch;
     L.key = take(batch ? 8 * (size_t)m : 0);
@@ -146,6 +170,12 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
     L.bitoff = take(batch ? 4 * (size_t)m : 0);
     L.gvoff = take(batch && o.have_vertex_side ? 4 * ((size_t)n + 1) : 0);
     L.ebase = take(batch && o.have_vertex_side ? 4 * (size_t)n : 0);
+    // An instance needs at most as many rounds as it has edges (each round
+    // matches its largest live edge).
+    L.solo_rounds = batch && o.solo_max_kappa >= 0
+                        ? (int)std::min<int64_t>(kSoloRounds, std::max<int64_t>(m, 1))
+                        : 0;
+    L.solo = take(L.solo_rounds ? 8 * ((size_t)kSoloHeader + 5 * (size_t)L.solo_rounds) : 0);
     L.total = at;
     return L;
 }
@@ -186,7 +216,11 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.wrange = (uint32_t *)(b + L.wrange);
     s.piece_cap = L.piece_cap;
     s.hub_threshold = o.hub_threshold;
+    s.hot_degree = o.hot_degree;
     s.vbits = (uint32_t *)(b + L.vbits);
+    s.explicit0 = L.solo_rounds > 0;
+    s.solo = L.solo_rounds ? (unsigned long long *)(b + L.solo) : nullptr;
+    s.solo_rounds = L.solo_rounds;
     return s;
 }
 
@@ -205,7 +239,10 @@ int next_batch(const Opts &o, int launched, const std::vector<int64_t> &live_pin
     if (!o.adaptive) return o.rounds_per_sync;
     if (launched == 0 || live_pins.size() < 2) {
         const double k0 = live_pins.empty() ? 2.0 : std::max<double>(2.0, (double)live_pins[0]);
-        const int first = (int)std::lround((graph ? 0.35 : 0.4) * std::log2(k0));
+        const int pct = o.first_batch_pct ? o.first_batch_pct
+                        : graph            ? kFirstBatchPctGraph
+                                           : kFirstBatchPct;
+        const int first = (int)std::lround(pct / 100.0 * std::log2(k0));
         return std::max(kFirstBatch, std::min(kAdaptiveMaxBatch, first));
     }
     const double cur = (double)live_pins.back();
@@ -267,7 +304,8 @@ int check_graph(const hgm_csr *g, const Opts &o) {
     return HGM_OK;
 }
 
-int device_grid() {
+// Compute units of the current device (0 on a HIP error).
+int device_cus() {
     static std::atomic<int> cached[64];  // zero-initialised (static storage)
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -279,9 +317,53 @@ int device_grid() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         return 0;
-    int grid = cus * kBlocksPerCu;
-    if (dev >= 0 && dev < 64) cached[dev].store(grid, std::memory_order_relaxed);
-    return grid;
+    if (dev >= 0 && dev < 64) cached[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
+// Workgroups of the solo kernel: one per compute unit (each holds up to the
+// whole LDS of its unit).
+int solo_workgroups() { return std::max(1, device_cus()); }
+
+// Dynamic LDS of a solo workgroup on the current device: all a workgroup may
+// hold less the solo kernel's own shared variables (a multiple of 256).
+int solo_lds_bytes() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < 64) {
+        const int c = cached[dev].load(std::memory_order_relaxed);
+        if (c) return c;
+    }
+    int bytes = 0;
+    if (hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        bytes <= kSoloStaticLds + 16384)
+        return 0;
+    const int dyn = (bytes - kSoloStaticLds) & ~255;
+    if (dev >= 0 && dev < 64) cached[dev].store(dyn, std::memory_order_relaxed);
+    return dyn;
+}
+
+// Best-tile vertices of an instance with nv vertices (k_solo's layout: the
+// done bitmask rounded up to 256 bytes, then the tile).
+int solo_tile(int lds_bytes, int64_t nv) {
+    const int64_t dbytes = ((4 * ((nv + 31) / 32) + 255) / 256) * 256;
+    return (int)std::max<int64_t>(0, (lds_bytes - dbytes) / 8);
+}
+
+// Largest vertex count whose instance needs at most `tiles` tiles.
+int solo_verts_for(int lds_bytes, int tiles) {
+    int64_t lo = 0, hi = (int64_t)lds_bytes * 8;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        const int t = solo_tile(lds_bytes, mid);
+        if (t > 0 && (mid + t - 1) / t <= tiles)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return (int)lo;
 }
 
 // Optional per-kernel timing: an event is recorded after every kernel (and
@@ -371,8 +453,15 @@ struct KernelTimer {
 
 // Enqueues setup and rounds, checking termination on the host every batch of
 // rounds; shared by the single-instance and the batched entry point.
+int solo_workgroups();
+
+// Rows of the solo part's per-round sums copied with its header at the first
+// termination check (more only when a solo instance ran more rounds).
+constexpr int kSoloRowsFirst = 64;
+
 int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s, const Launch &L,
-               uint32_t seed, uint32_t *matched_bits, hgm_stats *stats, const BatchIn *batch) {
+               uint32_t seed, uint32_t *matched_bits, hgm_stats *stats, const BatchIn *batch,
+               const SoloArgs *solo = nullptr) {
     int init_flags = 0;
     if (uses_live_key(o)) init_flags |= kInitLiveKey | (o.reseed ? kInitLiveMark : 0);
     // Priority seed of round r.
@@ -398,6 +487,16 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
     if (batch) HGM_TRY(launch_batch_setup(L, g, *batch, s));
     HGM_TRY(launch_init(L, g, seed, s, matched_bits, init_flags));
     HGM_TRY(T.after(HGM_K_SETUP, kSetup));
+    // Solo part of a batch: small instances run every round in one workgroup
+    // each; the round kernels then start from an explicit list of the rest.
+    const bool explicit0 = s.explicit0 != 0;
+    std::vector<unsigned long long> solo_head(kSoloHeader + 5 * (size_t)kSoloRowsFirst, 0);
+    if (explicit0) {
+        HGM_TRY(launch_solo(L, g, s, *solo, matched_bits, o.reseed ? 1 : 0, solo_workgroups()));
+        HGM_TRY(T.after(HGM_K_SOLO, kSetup));
+        HGM_TRY(launch_live0(L, g, s, *solo));
+        HGM_TRY(T.after(HGM_K_SETUP, kSetup));
+    }
     if (o.validate) {
         HGM_TRY(launch_validate(L, g, s, 1));
         HGM_TRY(T.after(HGM_K_SETUP, kSetup));
@@ -457,7 +556,7 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             // Clear the next round's max buffer when the next round scatters
             // (always in CRCW; at the switch from CREW to CRCW).
             const int clear = next_crew ? kClearNone
-                              : predicted_pins(r) * kFullClearRatio >= (double)g.n ? kClearAll
+                              : predicted_pins(r) * o.clear_ratio >= (double)g.n ? kClearAll
                                                                                     : kClearPins;
             HGM_TRY(launch_test(L, g, s, r, clear, matched_bits, kseed(r)));
             HGM_TRY(T.after(HGM_K_TEST, r));
@@ -477,12 +576,27 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                                    hipMemcpyDeviceToHost, L.stream));
             r += run;
         }
+        if (explicit0 && first == 0)
+            HGM_TRY(hipMemcpyAsync(solo_head.data(), s.solo,
+                                   sizeof(unsigned long long) * solo_head.size(),
+                                   hipMemcpyDeviceToHost, L.stream));
         HGM_TRY(hipStreamSynchronize(L.stream));
         auto sum = [](const unsigned long long *a) {
             unsigned long long t = 0;
             for (int i = 0; i < kSub; ++i) t += a[i];
             return t;
         };
+        if (explicit0 && first == 0) {
+            // The explicit round-0 list counted itself; an empty one means
+            // the solo part matched every instance.
+            live_e[0] = (int64_t)sum(ring[0].live);
+            live_p[0] = (int64_t)sum(ring[0].kappa);
+            if (live_e[0] == 0) {
+                finished = true;
+                rounds = 0;
+                launched = first;
+            }
+        }
         for (int r = first; r < launched; ++r) {
             const RoundStats &cur = ring[r % lay.ring];
             const RoundStats &nxt = ring[(r + 1) % lay.ring];
@@ -506,13 +620,48 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
         if (!finished && o.max_rounds > 0 && launched >= o.max_rounds) return HGM_E_ROUND_LIMIT;
     }
 
+    int64_t tm = 0;
+    uint64_t tw = 0;
+    for (int r = 0; r < rounds; ++r) {
+        tm += matched_r[r];
+        tw += weight_r[r];
+    }
+    if (explicit0 && g.m > 0) {
+        // Merge the solo part: its rounds count from each instance's own
+        // round 0, like the round kernels' rounds.
+        if (solo_head[1]) return HGM_E_ROUND_LIMIT;
+        const int sr = (int)solo_head[0];
+        const int rows = std::min(sr, lay.solo_rounds);
+        std::vector<unsigned long long> row(5 * (size_t)rows);
+        if (rows > kSoloRowsFirst) {
+            HGM_TRY(hipMemcpyAsync(row.data(), s.solo + kSoloHeader,
+                                   sizeof(unsigned long long) * row.size(),
+                                   hipMemcpyDeviceToHost, L.stream));
+            HGM_TRY(hipStreamSynchronize(L.stream));
+        } else if (rows > 0) {
+            std::copy(solo_head.begin() + kSoloHeader,
+                      solo_head.begin() + kSoloHeader + 5 * (size_t)rows, row.begin());
+        }
+        const int total = std::max(rounds, sr);
+        live_e.resize(std::max<size_t>(live_e.size(), (size_t)total), 0);
+        live_p.resize(std::max<size_t>(live_p.size(), (size_t)total), 0);
+        matched_r.resize(std::max<size_t>(matched_r.size(), (size_t)total), 0);
+        matched_p.resize(std::max<size_t>(matched_p.size(), (size_t)total), 0);
+        weight_r.resize(std::max<size_t>(weight_r.size(), (size_t)total), 0);
+        for (int r = 0; r < rows; ++r) {
+            live_e[r] += (int64_t)row[5 * r + 0];
+            live_p[r] += (int64_t)row[5 * r + 1];
+            matched_r[r] += (int64_t)row[5 * r + 2];
+            weight_r[r] += row[5 * r + 3];
+            matched_p[r] += (int64_t)row[5 * r + 4];
+        }
+        tm += (int64_t)solo_head[3];
+        tw += solo_head[4];
+        rounds = total;
+    }
     if (stats) {
         stats->rounds = rounds;
-        int64_t tm = 0;
-        uint64_t tw = 0;
         for (int r = 0; r < rounds; ++r) {
-            tm += matched_r[r];
-            tw += weight_r[r];
             if (r < stats->cap) {
                 if (stats->live_edges) stats->live_edges[r] = live_e[r];
                 if (stats->live_pins) stats->live_pins[r] = live_p[r];
@@ -584,7 +733,7 @@ int match_one(const hgm_csr *gin, uint32_t seed, uint32_t *matched_bits, void *w
     g.w = gin->w;
     const State s = carve(workspace, lay, o);
     Launch L;
-    L.grid = device_grid();
+    L.grid = device_cus() * o.blocks_per_cu;
     L.stream = (hipStream_t)stream;
     if (L.grid <= 0) return HGM_E_HIP;
     return run_rounds(g, o, lay, s, L, seed, matched_bits, stats, nullptr);
@@ -701,10 +850,30 @@ int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace,
     g.bitoff = in.bitoff;
     g.ebase = in.ebase;
     Launch L;
-    L.grid = device_grid();
+    L.grid = device_cus() * o.blocks_per_cu;
     L.stream = (hipStream_t)stream;
     if (L.grid <= 0) return HGM_E_HIP;
-    return run_rounds(g, o, lay, s, L, 0, matched_bits, stats, &in);
+    SoloArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    if (s.explicit0) {
+        sa.count = b->count;
+        sa.v_base = b->v_base;
+        sa.e_base = b->e_base;
+        sa.pin_base = b->pin_base;
+        sa.word_base = b->word_base;
+        sa.max_kappa = o.solo_max_kappa;
+        sa.lds_bytes = solo_lds_bytes();
+        if (sa.lds_bytes <= 0) return HGM_E_HIP;
+        sa.one_tile = solo_verts_for(sa.lds_bytes, 1);
+        sa.max_verts = solo_verts_for(sa.lds_bytes, kSoloMaxTiles);
+        sa.max_rounds = o.max_rounds;
+    }
+    return run_rounds(g, o, lay, s, L, 0, matched_bits, stats, &in, &sa);
+}
+
+int hgm_solo_lds_vertices(void) {
+    const int bytes = solo_lds_bytes();
+    return bytes > 0 ? solo_verts_for(bytes, 1) : 0;
 }
 
 }  // extern "C"

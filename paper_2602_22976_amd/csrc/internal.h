@@ -11,7 +11,6 @@ namespace hgm {
 constexpr int kBlock = 256;  // threads per workgroup = edges (or vertices) per chunk
 constexpr int kSub = 64;     // counters are spread over kSub addresses (one per 64 blocks)
 constexpr int kHubPiece = 8192;  // incidences of a hub vertex reduced by one workgroup
-constexpr int kHotDegree = 64;   // vertices at least this degree count as hot (round-0 choice)
 
 __host__ __device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) {
     return (x << r) | (x >> (32 - r));
@@ -127,7 +126,7 @@ struct State {
     int2 *pieces;       // [piece_cap] (hub vertex, piece index): the incidence list of a
                         // vertex of degree > hub threshold is cut into kHubPiece pieces
     int32_t *piece_count;  // [1]
-    unsigned long long *hot;  // [kSub] incidences on vertices of degree >= kHotDegree
+    unsigned long long *hot;  // [kSub] incidences on vertices of degree >= hot_degree
     uint32_t *wrange;   // [2 * kSub] smallest and largest weight (kInitWeightRange, or
                         // AUTO's round-0 edge kernel when the vertex form runs): slot
                         // k holds workgroups b = k mod kSub, min at 2k, max at 2k + 1
@@ -137,8 +136,48 @@ struct State {
     int32_t *vlen[2];   // [n] their counts
     int32_t piece_cap;
     int32_t hub_threshold;
+    int32_t hot_degree;  // vertices of at least this degree are hot (AUTO's round-0 form)
     uint32_t *vbits;    // [ceil(kappa/32)] validation: edge-side incidences seen
+    // Batch with a solo part: round 0's live list is not the identity but an
+    // explicit list[0] / cnt[0] with records, holding only the edges of the
+    // instances the round kernels match (the others ran in k_solo).
+    int32_t explicit0;
+    unsigned long long *solo;  // [kSoloHeader + 5 * solo_rounds] per-round sums of the solo
+                               // instances (see SoloArgs); NULL without a solo part
+    int32_t solo_rounds;       // rows of per-round sums
 };
+
+// Solo part of a batch: instances with at most max_kappa pins and at most
+// max_verts vertices are matched whole by one workgroup each (k_solo), every
+// round inside the workgroup.  Their done flags are a bitmask in LDS, and
+// best is kept in LDS in tiles of vertices: instances with at most one_tile
+// vertices need one tile, larger ones (up to kSoloMaxTiles tiles) form and
+// test each round's maximum tile by tile.  Per-round sums go to State::solo:
+// header word 0 = most rounds of any solo instance, word 1 = nonzero when an
+// instance reached max_rounds with live edges, word 2 = the work counter,
+// words 3 and 4 = matched edges and their weight over all rounds; then row r
+// holds live edges, live pins, matched edges, their weight and their pins of
+// round r summed over the solo instances (rows beyond solo_rounds are not
+// recorded; the host never asks for them).
+constexpr int kSoloHeader = 8;
+constexpr int kSoloThreads = 1024;
+constexpr int kSoloStaticLds = 24 * 1024;  // bound on k_solo's own shared variables
+constexpr int kSoloMaxTiles = 8;
+struct SoloArgs {
+    int32_t count;
+    const int64_t *v_base, *e_base, *pin_base, *word_base;  // the caller's [count + 1]
+    int64_t max_kappa;
+    int32_t max_verts;
+    int32_t one_tile;
+    int32_t lds_bytes;   // dynamic LDS of a workgroup: done bitmask, then best tiles
+    int32_t max_rounds;  // 0 = no limit
+};
+
+// Whether instance i of a batch (n_i vertices, kappa_i pins) is matched by k_solo.
+__host__ __device__ __forceinline__ bool solo_instance(int64_t n_i, int64_t kappa_i,
+                                                       const SoloArgs &a) {
+    return kappa_i <= a.max_kappa && n_i <= a.max_verts;
+}
 
 struct Launch {
     int grid;            // persistent workgroup count for vertex / setup kernels
@@ -158,6 +197,10 @@ constexpr int kInitLiveMark = 8;     // with kInitLiveKey: live_key = w << 32 | 
 hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const State &s,
                        uint32_t *bits, int init_flags);
 hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s);
+// Solo part of a batch, then the explicit round-0 list of the other instances.
+hipError_t launch_solo(const Launch &L, const Graph &g, const State &s, const SoloArgs &a,
+                       uint32_t *bits, int rekey, int workgroups);
+hipError_t launch_live0(const Launch &L, const Graph &g, const State &s, const SoloArgs &a);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed);
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,

@@ -25,6 +25,8 @@
 // go to stats[r % ring], spread over kSub addresses.  best[] is
 // double-buffered by round parity so that the test of round r can clear the
 // buffer round r+1 will fill.
+#include <atomic>
+
 #include "internal.h"
 
 namespace hgm {
@@ -266,14 +268,17 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
     const int words = s.ring * (int)(sizeof(RoundStats) / sizeof(unsigned long long));
     for (int i = threadIdx.x; i < words; i += blockDim.x) st[i] = 0;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !s.explicit0) {  // an explicit round-0 list counts itself
         s.stats[0].live[0] = (unsigned long long)g.m;
         s.stats[0].kappa[0] = g.m == 0 ? 0ull
                               : g.pairs ? 2ull * (unsigned long long)g.m
                                         : (unsigned long long)g.e_off[g.m];
+    }
+    if (threadIdx.x == 0) {
         *s.err = 0;
         *s.piece_count = 0;
     }
+    if (s.solo && threadIdx.x < kSoloHeader) s.solo[threadIdx.x] = 0;
     if (threadIdx.x < kSub) {
         s.hot[threadIdx.x] = 0;
         s.wrange[2 * threadIdx.x] = 0xFFFFFFFFu;
@@ -326,7 +331,9 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
     const int64_t words = g.words;
     const int64_t edges = (flags & kInitLiveKey) ? g.m : 0;  // edge-indexed work: live keys only
     const int64_t span = edges > g.n ? edges : g.n;
-    const int64_t top = span > words ? span : words;
+    const int64_t solo_words = s.solo ? 5 * (int64_t)s.solo_rounds : 0;
+    const int64_t top0 = span > words ? span : words;
+    const int64_t top = top0 > solo_words ? top0 : solo_words;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
         if (i < g.m && (flags & kInitLiveKey))
@@ -338,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
             s.done[i] = 0;
             if (flags & kInitHubs) {
                 const int deg = g.v_off[i + 1] - g.v_off[i];
-                if (deg >= kHotDegree) hot += (unsigned long long)deg;
+                if (deg >= s.hot_degree) hot += (unsigned long long)deg;
                 if (deg > s.hub_threshold) {
                     const int np = (deg + kHubPiece - 1) / kHubPiece;
                     const int q0 = atomicAdd(s.piece_count, np);
@@ -348,6 +355,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Graph g, uint32_t seed, State s
             }
         }
         if (i < words) bits[i] = 0;
+        if (i < solo_words) s.solo[kSoloHeader + i] = 0;
     }
     if (flags & kInitHubs) {
         hot = block_sum_u64(hot, sum_tmp);
@@ -405,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_validate(Graph g, State s, int check
 // ---------------------------------------------------------------------------
 // Region helpers: number of live edges of workgroup b in round r, and item i.
 __device__ __forceinline__ int region_count(const State &s, int m, int round, int b) {
-    if (round == 0) {
+    if (round == 0 && !s.explicit0) {
         const int64_t lo = (int64_t)b * s.region;
         const int64_t c = (int64_t)m - lo;
         return c <= 0 ? 0 : (c > s.region ? s.region : (int)c);
@@ -415,7 +423,7 @@ __device__ __forceinline__ int region_count(const State &s, int m, int round, in
 
 __device__ __forceinline__ int region_item(const State &s, int round, int b, int i) {
     const int64_t at = (int64_t)b * s.region + i;
-    return round == 0 ? (int)at : s.list[round & 1][at];
+    return (round == 0 && !s.explicit0) ? (int)at : s.list[round & 1][at];
 }
 
 // Edge i of workgroup b's live list of round r, offset layout: id, pin offset
@@ -436,7 +444,7 @@ __device__ __forceinline__ EdgeRec edge_rec(const Graph &g, const State &s, int 
                                             int i, uint32_t kseed, bool rekey, int key_round) {
     EdgeRec r;
     const int64_t at = (int64_t)b * s.region + i;
-    if (round == 0) {
+    if (round == 0 && !(kB && s.explicit0)) {
         r.e = (int)at;
         r.base = g.e_off[r.e];
         r.len = g.e_off[r.e + 1] - r.base;
@@ -886,7 +894,7 @@ __global__ void __launch_bounds__(kBlock) k_vertex_max(Graph g, State s, int rou
 // hot vertices whose entries stay in L2; the vertex-centric pass gathers one
 // weight per incidence with no atomics, which is faster when incidences are
 // spread evenly.  k_init counted the incidences of vertices of degree >=
-// kHotDegree; the edge form is taken when they are at least half of all.
+// the hot degree; the edge form is taken when they are at least half of all.
 // The edge form reduces the hubs' pins in each workgroup's hub table.
 // Two kernels, each running only when the form is its own: the edge form
 // with its hub table and the vertex form are compiled separately (one kernel
@@ -1169,6 +1177,486 @@ __global__ void __launch_bounds__(kBlock) k_batch_setup(Graph g, BatchIn b, Stat
     }
 }
 
+// ---------------------------------------------------------------------------
+// Solo part of a batch: one workgroup matches one small instance from its
+// first round to its last, with only workgroup barriers between the phases
+// of a round, so a small instance pays no kernel launch and no grid-wide
+// pass per round and ends its own rounds when its own live list is empty.
+// Workgroups take instances from a counter.  Round 0 starts with every edge
+// raising best at its pins; then each round:
+//   test    a live edge whose key equals best at every pin is matched: its
+//           bit is set and its pins are marked done (Algorithm 2, P_e = |e|)
+//   clear   best of the instance is zeroed
+//   retire  every other live edge with a done pin leaves the live list
+//           (soft delete); the survivors are compacted, in order, into the
+//           other list and raise best at their pins with their key of the
+//           next round (Algorithm 1's concurrent maximum)
+// Vertex ids inside an instance are its local ids, so best and done are
+// indexed by them directly: in LDS when the instance has at most lds_verts
+// vertices (kLds), else in the workspace's arrays at its vertex range.  The
+// lists are edge-local ids in list[0] / list[1] at the instance's edge range
+// (free until k_live0_place builds the round kernels' lists).
+constexpr int kSoloWaves = kSoloThreads / kWave;
+
+__device__ __forceinline__ int solo_exclusive_sum(int v, int *wave_tmp, int *total) {
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int incl = wave_inclusive_sum(v);
+    if (lane == kWave - 1) wave_tmp[wid] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kSoloWaves; ++i) {
+        const int x = wave_tmp[i];
+        off += (i < wid) ? x : 0;
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + incl - v;
+}
+
+__device__ __forceinline__ unsigned long long solo_sum(unsigned long long v,
+                                                       unsigned long long *tmp) {
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0) tmp[wid] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int i = 0; i < kSoloWaves; ++i) t += tmp[i];
+    __syncthreads();
+    return t;
+}
+
+// Key of (global) edge gl in round r of a batch.
+__device__ __forceinline__ uint64_t solo_key(const Graph &g, const State &s, int gl, int r,
+                                             bool rekey) {
+    return rekey ? round_key<true>(g, s, 0, r, gl) : s.key[gl];
+}
+
+// Shared memory of one chunk of kSoloThreads live edges (flattened pin loops).
+struct SoloChunk {
+    int start[kSoloThreads];   // exclusive scan of the pins each edge contributes
+    int base[kSoloThreads];    // offset of those pins in e_pins
+    uint64_t key[kSoloThreads];
+    int flag[kSoloThreads];
+    int wave_tmp[kSoloWaves];
+    unsigned long long sum_tmp[kSoloWaves];
+    int inst;
+};
+static_assert(sizeof(SoloChunk) + 256 <= kSoloStaticLds, "k_solo's shared variables");
+
+// Largest j in [0, kSoloThreads) with start[j] <= t.
+__device__ __forceinline__ int solo_find(const int *start, int t) {
+    int j = 0;
+#pragma unroll
+    for (int step = kSoloThreads / 2; step > 0; step >>= 1)
+        if (start[j + step] <= t) j += step;
+    return j;
+}
+
+// The kUnroll incidences t0, t0 + kSoloThreads, ... of a chunk: edge slot
+// j (-1 past the end) and pin, all loads issued before any is used.
+__device__ __forceinline__ void solo_pins(const SoloChunk &C, const int32_t *e_pins, int total,
+                                          int t0, int (&j)[kUnroll], int (&pin)[kUnroll]) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        const int t = t0 + u * kSoloThreads;
+        j[u] = t < total ? solo_find(C.start, t) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+        pin[u] = j[u] >= 0 ? e_pins[C.base[j[u]] + (t0 + u * kSoloThreads - C.start[j[u]])] : 0;
+}
+
+__device__ __forceinline__ bool bit_is_set(const uint32_t *bits, int v) {
+    return (bits[v >> 5] >> (v & 31)) & 1u;
+}
+
+// One instance, every round, in this workgroup.  The instance's vertex ids
+// are its local ids.  done is a bitmask in LDS; best is kept in LDS in tiles
+// of `tile` vertices.  With one tile (most instances) a round is: test (first
+// pin per lane, the rest of the undecided edges spread over the workgroup),
+// clear, and retire fused with the next round's maximum.  With several tiles
+// a round first forms the maximum and tests it tile by tile, each pass
+// streaming the live pins and keeping those inside the tile, the failed
+// tests collected in a flag per live edge (in the workspace); then matched
+// edges are marked and the retire pass compacts the survivors.
+__device__ __forceinline__ void solo_run(const Graph &g, const State &s, const SoloArgs &a,
+                                         uint32_t *bits, bool rekey, int inst,
+                                         unsigned char *lds, SoloChunk &C) {
+    const int tid = threadIdx.x;
+    const int64_t v0 = a.v_base[inst], e0 = a.e_base[inst];
+    const int nv = (int)(a.v_base[inst + 1] - v0);
+    const int ne = (int)(a.e_base[inst + 1] - e0);
+    const int64_t bit0 = 32 * a.word_base[inst];
+    const int32_t *e_pins = g.e_pins;
+    const int dwords = (nv + 31) >> 5;
+    uint32_t *done = reinterpret_cast<uint32_t *>(lds);
+    const int dbytes = ((4 * dwords + 255) / 256) * 256;
+    uint64_t *best = reinterpret_cast<uint64_t *>(lds + dbytes);
+    const int tile = (a.lds_bytes - dbytes) / 8;
+    const int tiles = (nv + tile - 1) / tile;
+    const bool one = tiles <= 1;
+    int32_t *const list0 = s.list[0] + e0, *const list1 = s.list[1] + e0;
+    int32_t *const fail = s.rec_a[0] + e0;  // per live position (several tiles)
+    for (int w = tid; w < dwords; w += kSoloThreads) done[w] = 0;
+
+    // Raises best[pin - lo] to each chunk edge's key at its pins in [lo, hi).
+    auto scatter = [&](int total, int lo, int hi) {
+        for (int t0 = tid; t0 < total; t0 += kUnroll * kSoloThreads) {
+            int j[kUnroll], pin[kUnroll];
+            solo_pins(C, e_pins, total, t0, j, pin);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (j[u] >= 0 && pin[u] >= lo && pin[u] < hi)
+                    atomicMax((unsigned long long *)&best[pin[u] - lo],
+                              (unsigned long long)C.key[j[u]]);
+        }
+    };
+    // Chunk of live edges c0.. of list `in` (identity in round 0): loads one
+    // edge per lane and scans `contrib` of the pins into C (start, base).
+    auto edge_of = [&](const int32_t *in, int r, int j, int &e, int &base, int &len) {
+        e = r == 0 ? j : in[j];
+        const int gl = (int)e0 + e;
+        base = g.e_off[gl];
+        len = g.e_off[gl + 1] - base;
+    };
+    // Sets the bit, counts and marks the pins of matched edge e.
+    unsigned long long nm = 0, wm = 0, pm = 0;
+    auto record = [&](int e, int base, int len, uint64_t key) {
+        const int64_t bit = bit0 + e;
+        atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+        nm += 1;
+        wm += key >> 32;
+        pm += (unsigned long long)len;
+        for (int k0 = 0; k0 < len; k0 += kUnroll) {
+            int p[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) p[u] = k0 + u < len ? e_pins[base + k0 + u] : -1;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (p[u] >= 0) atomicOr(&done[p[u] >> 5], 1u << (p[u] & 31));
+        }
+    };
+    // The maximum of round r over the tile [lo, hi) of the live edges.
+    auto max_pass = [&](const int32_t *in, int r, int E, int lo, int hi) {
+        for (int c0 = 0; c0 < E; c0 += kSoloThreads) {
+            const int j = c0 + tid;
+            int e = 0, base = 0, len = 0;
+            uint64_t key = 0;
+            if (j < E) {
+                edge_of(in, r, j, e, base, len);
+                key = solo_key(g, s, (int)e0 + e, r, rekey);
+            }
+            int total;
+            const int st = solo_exclusive_sum(len, C.wave_tmp, &total);
+            C.start[tid] = st;
+            C.base[tid] = base;
+            C.key[tid] = key;
+            __syncthreads();
+            scatter(total, lo, hi);
+            __syncthreads();
+        }
+    };
+    auto clear_tile = [&](int n) {
+        for (int v = tid; v < n; v += kSoloThreads) best[v] = 0;
+        __syncthreads();
+    };
+
+    if (one) {  // round 0's maximum: every edge at every pin
+        clear_tile(nv);
+        max_pass(list0, 0, ne, 0, nv);
+    } else {
+        __syncthreads();
+    }
+    int E = ne;
+    unsigned long long K = (unsigned long long)(a.pin_base[inst + 1] - a.pin_base[inst]);
+    unsigned long long tot_m = 0, tot_w = 0;  // the instance's matched edges and weight
+    int r = 0;
+    for (;;) {
+        const int32_t *in = (r & 1) ? list1 : list0;
+        nm = wm = pm = 0;
+        if (one) {
+            // ---- test: the first pin per lane (most edges fail there), the
+            // remaining pins of the undecided edges spread over the workgroup
+            for (int c0 = 0; c0 < E; c0 += kSoloThreads) {
+                const int j = c0 + tid;
+                int e = -1, base = 0, len = 0;
+                uint64_t key = 0;
+                bool ok = false;
+                if (j < E) {
+                    edge_of(in, r, j, e, base, len);
+                    key = solo_key(g, s, (int)e0 + e, r, rekey);
+                    ok = len == 0 || best[e_pins[base]] == key;
+                }
+                int total;
+                const int st = solo_exclusive_sum(ok && len > 1 ? len - 1 : 0, C.wave_tmp, &total);
+                if (total > 0) {
+                    C.start[tid] = st;
+                    C.base[tid] = base + 1;
+                    C.key[tid] = key;
+                    C.flag[tid] = 0;
+                    __syncthreads();
+                    for (int t0 = tid; t0 < total; t0 += kUnroll * kSoloThreads) {
+                        int jj[kUnroll], pin[kUnroll];
+                        solo_pins(C, e_pins, total, t0, jj, pin);
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            if (jj[u] >= 0 && best[pin[u]] != C.key[jj[u]]) C.flag[jj[u]] = 1;
+                    }
+                    __syncthreads();
+                    ok = ok && !C.flag[tid];
+                    __syncthreads();
+                }
+                if (ok) record(e, base, len, key);
+            }
+        } else {
+            // ---- maximum and test tile by tile
+            for (int j = tid; j < E; j += kSoloThreads) fail[j] = 0;
+            for (int t = 0; t < tiles; ++t) {
+                const int lo = t * tile, hi = min(nv, lo + tile);
+                clear_tile(hi - lo);
+                max_pass(in, r, E, lo, hi);
+                for (int c0 = 0; c0 < E; c0 += kSoloThreads) {
+                    const int j = c0 + tid;
+                    int e = 0, base = 0, len = 0;
+                    uint64_t key = 0;
+                    if (j < E) {
+                        edge_of(in, r, j, e, base, len);
+                        key = solo_key(g, s, (int)e0 + e, r, rekey);
+                    }
+                    int total;
+                    const int st = solo_exclusive_sum(len, C.wave_tmp, &total);
+                    C.start[tid] = st;
+                    C.base[tid] = base;
+                    C.key[tid] = key;
+                    C.flag[tid] = 0;
+                    __syncthreads();
+                    for (int t0 = tid; t0 < total; t0 += kUnroll * kSoloThreads) {
+                        int jj[kUnroll], pin[kUnroll];
+                        solo_pins(C, e_pins, total, t0, jj, pin);
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            if (jj[u] >= 0 && pin[u] >= lo && pin[u] < hi &&
+                                best[pin[u] - lo] != C.key[jj[u]])
+                                C.flag[jj[u]] = 1;
+                    }
+                    __syncthreads();
+                    if (j < E && C.flag[tid]) fail[j] = 1;
+                    __syncthreads();
+                }
+            }
+            for (int j = tid; j < E; j += kSoloThreads) {
+                if (fail[j]) continue;
+                int e, base, len;
+                edge_of(in, r, j, e, base, len);
+                record(e, base, len, solo_key(g, s, (int)e0 + e, r, rekey));
+            }
+        }
+        nm = solo_sum(nm, C.sum_tmp);
+        wm = solo_sum(wm, C.sum_tmp);
+        pm = solo_sum(pm, C.sum_tmp);
+        tot_m += nm;
+        tot_w += wm;
+        if (tid == 0 && r < s.solo_rounds) {
+            unsigned long long *row = s.solo + kSoloHeader + 5 * (int64_t)r;
+            atomicAdd(&row[0], (unsigned long long)E);
+            atomicAdd(&row[1], K);
+            if (nm) {
+                atomicAdd(&row[2], nm);
+                atomicAdd(&row[3], wm);
+                atomicAdd(&row[4], pm);
+            }
+        }
+        // ---- clear the maximum for the next round (one tile; the test's
+        // reads are done); the done marks are complete after the barrier
+        if (one)
+            clear_tile(nv);
+        else
+            __syncthreads();
+        // ---- retire and compaction (with one tile also the next maximum)
+        const int rn = r + 1;
+        int32_t *out = (rn & 1) ? list1 : list0;
+        int kept = 0;
+        unsigned long long kn = 0;
+        for (int c0 = 0; c0 < E; c0 += kSoloThreads) {
+            const int j = c0 + tid;
+            int e = -1, base = 0, len = 0;
+            bool dead = true;
+            if (j < E) {
+                edge_of(in, r, j, e, base, len);
+                dead = len == 0;  // an empty edge was matched by its test
+                int p[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) p[u] = u < len ? e_pins[base + u] : -1;
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) dead = dead || (p[u] >= 0 && bit_is_set(done, p[u]));
+            }
+            int total;
+            const int st = solo_exclusive_sum(!dead && len > kUnroll ? len - kUnroll : 0,
+                                              C.wave_tmp, &total);
+            if (total > 0) {
+                C.start[tid] = st;
+                C.base[tid] = base + kUnroll;
+                C.flag[tid] = 0;
+                __syncthreads();
+                for (int t0 = tid; t0 < total; t0 += kUnroll * kSoloThreads) {
+                    int jj[kUnroll], pin[kUnroll];
+                    solo_pins(C, e_pins, total, t0, jj, pin);
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u)
+                        if (jj[u] >= 0 && bit_is_set(done, pin[u])) C.flag[jj[u]] = 1;
+                }
+                __syncthreads();
+                dead = dead || C.flag[tid];
+                __syncthreads();
+            }
+            const bool alive = !dead;
+            int n_alive;
+            const int pos = solo_exclusive_sum(alive ? 1 : 0, C.wave_tmp, &n_alive);
+            int total2;
+            const int st2 = solo_exclusive_sum(alive ? len : 0, C.wave_tmp, &total2);
+            if (alive) out[kept + pos] = e;
+            if (one) {
+                C.start[tid] = st2;
+                C.base[tid] = base;
+                C.key[tid] = alive ? solo_key(g, s, (int)e0 + e, rn, rekey) : 0;
+                __syncthreads();
+                scatter(total2, 0, nv);
+                __syncthreads();
+            }
+            kept += n_alive;
+            kn += (unsigned long long)total2;
+        }
+        K = kn;
+        E = kept;
+        r = rn;
+        if (E == 0) break;
+        if (a.max_rounds > 0 && r >= a.max_rounds) {
+            if (tid == 0) atomicOr(&s.solo[1], 1ull);
+            break;
+        }
+    }
+    if (tid == 0) {
+        atomicMax(&s.solo[0], (unsigned long long)r);
+        if (tot_m) {
+            atomicAdd(&s.solo[3], tot_m);
+            atomicAdd(&s.solo[4], tot_w);
+        }
+    }
+    // The instance is finished for the round kernels: every vertex done, so
+    // the vertex-centric passes of the batch skip it.
+    for (int v = tid; v < nv; v += kSoloThreads) s.done[v0 + v] = 1;
+    __syncthreads();
+}
+
+// Instances are taken largest-first in two sweeps of one counter: sweep 0
+// takes the instances that need several LDS tiles, sweep 1 the others, so
+// the longest ones do not start last.
+__global__ void __launch_bounds__(kSoloThreads) k_solo(Graph g, State s, SoloArgs a,
+                                                       uint32_t *bits, int rekey) {
+    extern __shared__ unsigned char solo_lds[];
+    __shared__ SoloChunk C;
+    for (;;) {
+        if (threadIdx.x == 0) C.inst = (int)atomicAdd(&s.solo[2], 1ull);
+        __syncthreads();
+        const int q = C.inst;
+        __syncthreads();  // every thread has read the index before it is overwritten
+        if (q >= 2 * a.count) break;
+        const int i = q < a.count ? q : q - a.count;
+        if (!solo_instance(a.v_base[i + 1] - a.v_base[i], a.pin_base[i + 1] - a.pin_base[i], a))
+            continue;
+        if (a.e_base[i + 1] == a.e_base[i]) continue;  // no edges: nothing to match
+        const bool big = a.v_base[i + 1] - a.v_base[i] > a.one_tile;
+        if (big != (q < a.count)) continue;
+        solo_run(g, s, a, bits, rekey != 0, i, solo_lds, C);
+    }
+}
+
+// Round 0's explicit live list for the round kernels: the edges of the
+// instances outside the solo part, with their records (pin offset, count,
+// first pin, vertex base, key), spread evenly over the workgroups' regions
+// in edge order (the rounds' cost follows the fullest region, and the solo
+// part leaves the remaining edges unevenly spread over the id range).  Two
+// passes: each workgroup counts the kept edges of its own id range into
+// cnt[1] (free until round 1's retire), then places them by global rank.
+__device__ __forceinline__ bool live0_keep(const SoloArgs &a, int &i, int64_t e) {
+    while (i + 1 < a.count && a.e_base[i + 1] <= e) ++i;
+    return !solo_instance(a.v_base[i + 1] - a.v_base[i], a.pin_base[i + 1] - a.pin_base[i], a);
+}
+
+__global__ void __launch_bounds__(kBlock) k_live0_count(Graph g, State s, SoloArgs a) {
+    __shared__ int first;
+    __shared__ unsigned long long sum_tmp[kWaves];
+    const int b = blockIdx.x;
+    const int64_t lo = (int64_t)b * s.region;
+    const int64_t hi = lo + s.region < (int64_t)g.m ? lo + s.region : (int64_t)g.m;
+    unsigned long long kept = 0;
+    if (lo < hi) {
+        if (threadIdx.x == 0) first = instance_of(a.e_base, a.count, lo);
+        __syncthreads();
+        int i = first;
+        for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock) kept += live0_keep(a, i, e) ? 1 : 0;
+    }
+    kept = block_sum_u64(kept, sum_tmp);
+    if (threadIdx.x == 0) s.cnt[1][b] = (int)kept;
+}
+
+__global__ void __launch_bounds__(kBlock) k_live0_place(Graph g, State s, SoloArgs a) {
+    __shared__ int first;
+    __shared__ int wave_tmp[kWaves];
+    __shared__ unsigned long long sum_tmp[kWaves];
+    const int b = blockIdx.x;
+    // Kept edges before this workgroup's range, and in all.
+    unsigned long long before = 0, all = 0;
+    for (int q = threadIdx.x; q < s.grid; q += kBlock) {
+        const unsigned long long c = (unsigned long long)s.cnt[1][q];
+        all += c;
+        before += q < b ? c : 0;
+    }
+    before = block_sum_u64(before, sum_tmp);
+    all = block_sum_u64(all, sum_tmp);
+    const int64_t per = ((int64_t)all + s.grid - 1) / s.grid;  // <= region (all <= m)
+    const int64_t lo = (int64_t)b * s.region;
+    const int64_t hi = lo + s.region < (int64_t)g.m ? lo + s.region : (int64_t)g.m;
+    unsigned long long kap = 0;
+    int64_t rank = (int64_t)before;
+    if (lo < hi) {
+        if (threadIdx.x == 0) first = instance_of(a.e_base, a.count, lo);
+        __syncthreads();
+        int i = first;
+        for (int64_t c0 = lo; c0 < hi; c0 += kBlock) {
+            const int64_t e = c0 + threadIdx.x;
+            const bool keep = e < hi && live0_keep(a, i, e);
+            int total;
+            const int pos = block_exclusive_sum(keep ? 1 : 0, wave_tmp, &total);
+            if (keep) {
+                const int64_t q = rank + pos;
+                const int64_t at = (q / per) * s.region + q % per;
+                const int base = g.e_off[e], len = g.e_off[e + 1] - base;
+                const int vb = g.vbase[e];
+                s.list[0][at] = (int)e;
+                s.rec_a[0][at] = base;
+                s.rec_b[0][at] = len;
+                s.rec_c[0][at] = len > 0 ? g.e_pins[base] + vb : -1;
+                s.rec_vb[0][at] = vb;
+                s.rec_key[0][at] = s.key[e];
+                kap += (unsigned long long)len;
+            }
+            rank += total;
+        }
+    }
+    kap = block_sum_u64(kap, sum_tmp);
+    if (threadIdx.x == 0) {
+        const int64_t mine = (int64_t)all - (int64_t)b * per;
+        s.cnt[0][b] = (int)(mine <= 0 ? 0 : mine < per ? mine : per);
+        if (kap > 0) atomicAdd(&s.stats[0].kappa[b % kSub], kap);
+        if (b == 0 && all > 0) atomicAdd(&s.stats[0].live[0], all);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_zero_words(uint32_t *p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
@@ -1187,6 +1675,27 @@ hipError_t launch_init(const Launch &L, const Graph &g, uint32_t seed, const Sta
 hipError_t launch_batch_setup(const Launch &L, const Graph &g, const BatchIn &b, const State &s) {
     if (b.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_batch_setup, dim3(L.grid), dim3(kBlock), 0, L.stream, g, b, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_solo(const Launch &L, const Graph &g, const State &s, const SoloArgs &a,
+                       uint32_t *bits, int rekey, int workgroups) {
+    const size_t lds = (size_t)a.lds_bytes;
+    static std::atomic<size_t> granted{0};
+    if (granted.load(std::memory_order_relaxed) < lds) {
+        hipError_t rc = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_solo),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (rc != hipSuccess) return rc;
+        granted.store(lds, std::memory_order_relaxed);
+    }
+    hipLaunchKernelGGL(k_solo, dim3(workgroups), dim3(kSoloThreads), lds, L.stream, g, s, a, bits,
+                       rekey);
+    return hipGetLastError();
+}
+
+hipError_t launch_live0(const Launch &L, const Graph &g, const State &s, const SoloArgs &a) {
+    hipLaunchKernelGGL(k_live0_count, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, a);
+    hipLaunchKernelGGL(k_live0_place, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, a);
     return hipGetLastError();
 }
 

@@ -135,6 +135,44 @@ def test_noalloc_arguments_without_gpu(lib):
     assert hgm.hgm_match_noalloc(_csr(5, 5, 5), 1, bits, None, 0, st) == hgm.HGM_E_ARG
 
 
+def test_schedule_options_without_gpu(lib):
+    """Schedule fields out of range are refused; the tuner's workspace covers
+    its largest candidate edge grid."""
+    c = _csr(2_000_000, 5_000_000, 30_000_000)
+    for kw in (dict(edge_grid=-1), dict(edge_grid=65537), dict(blocks_per_cu=33),
+               dict(clear_ratio=-2), dict(hot_degree=-1), dict(first_batch_pct=401),
+               dict(solo_max_kappa=-2)):
+        assert hgm.hgm_workspace_size(c, hgm.make_opts(**kw)) == 0, kw
+    assert hgm.hgm_workspace_size(c, hgm.make_opts(edge_grid=65536, blocks_per_cu=32)) > 0
+    base = hgm.hgm_workspace_size(c)
+    t = lib.hgm_tune_workspace_size(ctypes.byref(c), None)
+    assert t >= base and t >= hgm.hgm_workspace_size(c, hgm.make_opts(edge_grid=4096))
+
+
+def test_tune_cache_lookup_without_gpu(lib, tmp_path):
+    """The cache is a text file of `key : name=value ...` lines; without a
+    device the key's device part reads "unknown".  A line for the instance's
+    bucket fills the schedule fields; other buckets and a missing file leave
+    the options unchanged."""
+    c = _csr(10_000, 20_000, 100_000)      # round(log2 kappa) = 17, mean size 5
+    path = tmp_path / "cache.txt"
+    path.write_text("unknown match v0 p0 r0 k17 d5 c0 : solo=1 grid=512 bpc=4 hub=1024 hot=16 "
+                    "clear=2 first=25 ms_default=1 ms_tuned=0.5\n"
+                    "unknown match v2 p0 r0 k17 d5 c0 : grid=4096\n")
+    o = hgm.make_opts("auto")
+    assert lib.hgm_tuned_opts(str(path).encode(), ctypes.byref(c), ctypes.byref(o)) == 0
+    assert (o.edge_grid, o.blocks_per_cu, o.hub_threshold, o.hot_degree, o.clear_ratio,
+            o.first_batch_pct) == (512, 4, 1024, 16, 2, 25)
+    o = hgm.make_opts("crew")
+    assert lib.hgm_tuned_opts(str(path).encode(), ctypes.byref(c), ctypes.byref(o)) == 0
+    assert o.edge_grid == 4096 and o.blocks_per_cu == 0
+    o = hgm.make_opts("crcw")
+    assert lib.hgm_tuned_opts(str(path).encode(), ctypes.byref(c), ctypes.byref(o)) == -1
+    assert o.edge_grid == 0
+    assert lib.hgm_tuned_opts(str(tmp_path / "none.txt").encode(), ctypes.byref(c),
+                              ctypes.byref(o)) == -1
+
+
 def test_product_package_does_not_use_the_oracle():
     pkg = os.path.join(ROOT, "paper_2602_22976_amd")
     for dirpath, _, files in os.walk(pkg):

@@ -1,7 +1,9 @@
 """GPU parity of hgm_match_batch: every instance's bitmap segment equals the
 oracle's greedy matching for that instance and seed, and equals hgm_match on
 the instance alone; the aggregate per-round counts equal the sum of the
-instances' oracle round counts."""
+instances' oracle round counts.  Batches run with the one-workgroup solo part
+for small instances at its default bound (SOLO 0), with a low bound so that
+solo and round-kernel instances mix (2000 pins), and without it (-1)."""
 import time
 
 import numpy as np
@@ -13,6 +15,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 VARIANTS = ["auto", "crcw", "crew"]
+SOLO = [0, 2000, -1]
 
 
 @pytest.fixture(scope="module")
@@ -74,15 +77,18 @@ def _check_batch(hgm, b, variant, per=None, rounds=None, **kw):
     return got
 
 
+@pytest.mark.parametrize("solo", SOLO)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_small_batch(hgm, variant):
+def test_small_batch(hgm, variant, solo):
     b = synth.config_batched(seed=77, count=96, n_lo=20, n_hi=3000)
-    print(f"batch count={b.count} m_total={int(b.e_base[-1])} variant={variant}", flush=True)
-    _check_batch(hgm, b, variant)
+    print(f"batch count={b.count} m_total={int(b.e_base[-1])} variant={variant} solo={solo}",
+          flush=True)
+    _check_batch(hgm, b, variant, solo_max_kappa=solo)
 
 
+@pytest.mark.parametrize("solo", SOLO)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_degenerate_batches(hgm, variant):
+def test_degenerate_batches(hgm, variant, solo):
     rng = np.random.default_rng(3)
     gs = [synth.from_edge_lists(0, [], []),                          # empty instance
           synth.random_instance(5, 40, 70, 2, 4, 1, 9),
@@ -92,14 +98,15 @@ def test_degenerate_batches(hgm, variant):
           synth.from_edge_lists(1, [[0]], [3])]
     seeds = rng.integers(0, 2 ** 32, size=len(gs)).astype(np.uint32)
     b = synth.batch_from_instances(gs, seeds)
-    print(f"degenerate batch variant={variant}", flush=True)
-    _check_batch(hgm, b, variant)
+    print(f"degenerate batch variant={variant} solo={solo}", flush=True)
+    _check_batch(hgm, b, variant, solo_max_kappa=solo)
     one = synth.batch_from_instances([gs[1]], seeds[:1])
-    _check_batch(hgm, one, variant)
+    _check_batch(hgm, one, variant, solo_max_kappa=solo)
 
 
+@pytest.mark.parametrize("solo", SOLO)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_skewed_batch(hgm, variant):
+def test_skewed_batch(hgm, variant, solo):
     """One large instance among thousands of tiny and empty ones, in three
     orders (large first, in the middle, last): the setup's workgroups each
     take an equal range of edges and of vertices, so one range spans dozens
@@ -123,13 +130,15 @@ def test_skewed_batch(hgm, variant):
         gs = tiny[:at] + [big] + tiny[at:]
         seeds = rng.integers(0, 2 ** 32, size=len(gs)).astype(np.uint32)
         b = synth.batch_from_instances(gs, seeds)
-        print(f"skewed batch: large instance at {at}, variant={variant}", flush=True)
-        _check_batch(hgm, b, variant)
+        print(f"skewed batch: large instance at {at}, variant={variant} solo={solo}",
+              flush=True)
+        _check_batch(hgm, b, variant, solo_max_kappa=solo)
 
 
+@pytest.mark.parametrize("solo", [0, -1])
 @pytest.mark.parametrize("variant", ["auto", "crew"])
 @pytest.mark.parametrize("threshold", [0, 64, 300])
-def test_dense_batch_takes_the_edge_form(hgm, threshold, variant):
+def test_dense_batch_takes_the_edge_form(hgm, threshold, variant, solo):
     """Dense instances (every vertex of degree about 100), so AUTO's round 0
     takes the edge-centric form over the batch; with a low hub threshold the
     high-degree vertices become hubs reduced in each workgroup's table
@@ -144,8 +153,8 @@ def test_dense_batch_takes_the_edge_form(hgm, threshold, variant):
     b = synth.batch_from_instances(gs, seeds)
     deg = np.concatenate([np.diff(b.instance(i).v_off) for i in range(b.count)])
     assert 2 * int(deg[deg >= 64].sum()) >= int(b.pin_base[-1])   # AUTO's edge-form condition
-    print(f"dense batch hub_threshold={threshold} variant={variant}", flush=True)
-    _check_batch(hgm, b, variant, hub_threshold=threshold)
+    print(f"dense batch hub_threshold={threshold} variant={variant} solo={solo}", flush=True)
+    _check_batch(hgm, b, variant, hub_threshold=threshold, solo_max_kappa=solo)
 
 
 def test_batch_equals_single_calls(hgm):
@@ -169,8 +178,68 @@ def test_batch_workload_sample(hgm):
     print(f"batched workload sample: m_total={int(b.e_base[-1])} "
           f"kappa_total={int(b.pin_base[-1])}", flush=True)
     per, rounds = _oracle_batch(b)
-    for variant in ("auto", "crcw"):
-        _check_batch(hgm, b, variant, per, rounds)
+    for variant, solo in (("auto", 0), ("crcw", -1), ("crew", 30000), ("auto", 2000)):
+        print(f"batched workload sample variant={variant} solo={solo}", flush=True)
+        _check_batch(hgm, b, variant, per, rounds, solo_max_kappa=solo)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_solo_instances_beyond_lds(hgm, variant):
+    """Instances with more vertices than one LDS tile of the solo part (it
+    then forms and tests each round's maximum tile by tile: 2, 3 and 8
+    tiles) among instances that fit one tile, one with more pins than the
+    solo bound and one with more than 8 tiles' worth of vertices (both taken
+    by the round kernels)."""
+    lds = hgm.load().hgm_solo_lds_vertices()
+    assert lds >= 4096
+    gs, seeds = [], []
+    sizes = [lds + 1, lds // 2, 2 * lds + 100, lds // 3, lds, 5 * lds]
+    for k, n in enumerate(sizes):
+        gs.append(synth.random_instance(900 + k, n, 2 * n, 2, 10, 1, 1 if k == 4 else 1000))
+        seeds.append(31 * k + 1)
+    gs.append(synth.random_instance(940, 8 * lds - 2000, 2 * lds, 2, 6, 1, 1000))  # 8 tiles
+    seeds.append(77)
+    gs.append(synth.random_instance(941, 9 * lds, lds, 2, 6, 1, 1000))     # beyond 8 tiles
+    seeds.append(78)
+    gs.append(synth.random_instance(950, 3 * lds, 12 * lds, 2, 10, 1, 1000))
+    seeds.append(99)
+    b = synth.batch_from_instances(gs, np.array(seeds, dtype=np.uint32))
+    kap = np.diff(b.pin_base)
+    bound = int(kap[:-1].max())
+    assert kap[-1] > bound           # the last one runs in the round kernels
+    print(f"solo beyond LDS: lds_verts={lds} variant={variant}", flush=True)
+    _check_batch(hgm, b, variant, solo_max_kappa=bound)
+
+
+@pytest.mark.parametrize("solo", SOLO)
+def test_batch_round_limit(hgm, solo):
+    """A path with increasing weights needs 101 rounds: with max_rounds 50
+    the batch fails with HGM_E_ROUND_LIMIT whichever part runs it, and with
+    max_rounds 101 it completes."""
+    from tests.fixtures import path_graph
+    import torch
+    gs = [synth.random_instance(3, 300, 600, 2, 5, 1, 50), path_graph(201)]
+    b = synth.batch_from_instances(gs, np.array([1, 2], dtype=np.uint32))
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    with pytest.raises(hgm.HgmError) as ei:
+        hgm.match_batch(db, hgm.make_opts("auto", max_rounds=50, solo_max_kappa=solo))
+    assert ei.value.code == hgm.HGM_E_ROUND_LIMIT
+    torch.cuda.synchronize()
+    _check_batch(hgm, b, "auto", max_rounds=101, solo_max_kappa=solo)
+
+
+def test_solo_part_is_used(hgm):
+    """Timing statistics show the solo kernel once per call when instances
+    fit its bound, and the round kernels alone when it is off."""
+    import torch
+    b = synth.config_batched(seed=78, count=64, n_lo=20, n_hi=2000)
+    db = hgm.DeviceBatch.from_host(b, "cuda:0")
+    _, st = hgm.match_batch(db, hgm.make_opts("auto"), timing=True)
+    assert st["kernel_launches"]["solo"] == 1 and st["kernel_ms"]["solo"] > 0
+    assert st["kernel_launches"]["test"] == 0     # every instance ran in the solo part
+    _, st = hgm.match_batch(db, hgm.make_opts("auto", solo_max_kappa=-1), timing=True)
+    assert st["kernel_launches"]["solo"] == 0 and st["kernel_launches"]["test"] > 0
+    torch.cuda.synchronize()
 
 
 def test_batch_full_workload(hgm):
