@@ -189,6 +189,18 @@ def batched_leg(count, steps):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
     batch_bits = bits.clone()
+    _, sti = hgm.match_batch(db, opts, workspace=ws, bits=bits, timing=True)
+    off = hgm.make_opts("auto", solo_max_kappa=-1)   # the round kernels alone
+    ws_off = hgm.alloc_batch_workspace(db, off)
+    hgm.match_batch(db, off, workspace=ws_off, bits=bits, want_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hgm.match_batch(db, off, workspace=ws_off, bits=bits, want_stats=False)
+    torch.cuda.synchronize()
+    t_rounds_only = (time.perf_counter() - t0) / steps
+    same_off = bool(torch.equal(bits, batch_bits))
+    del ws_off
 
     views = []
     wmax = 0
@@ -215,7 +227,11 @@ def batched_leg(count, steps):
             "ms_batched": t_batch * 1e3, "ms_plain": t_plain * 1e3,
             "hypergraphs_per_s_batched": count / t_batch,
             "hypergraphs_per_s_plain": count / t_plain,
-            "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same}
+            "batched_over_plain": t_plain / t_batch, "plain_equals_batched": same,
+            "solo_ms": sti["kernel_ms"]["solo"],
+            "kernel_ms": {k: round(v, 3) for k, v in sti["kernel_ms"].items()},
+            "ms_round_kernels_only": t_rounds_only * 1e3,
+            "round_kernels_only_equal": same_off}
 
 
 def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
@@ -233,21 +249,7 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
     import paper_2602_22976_amd as hgm
     import synth
     t0 = time.perf_counter()
-    pool = synth.config_served_pool(seed=1005, count=pool_count)
-    pinned = []
-    for g in pool:   # copy every array into pinned host memory (asynchronous uploads)
-        arrs = {}
-        for name in ("e_off", "e_pins", "v_off", "v_edges"):
-            t = torch.empty(getattr(g, name).size, dtype=torch.int32, pin_memory=True)
-            t.numpy()[:] = getattr(g, name)
-            arrs[name] = t
-        t = torch.empty(g.m, dtype=torch.int32, pin_memory=True)
-        t.numpy()[:] = g.w.view(np.int32)
-        arrs["w"] = t
-        pinned.append((g, arrs))
-    views = [synth.Hypergraph(g.n, g.m, a["e_off"].numpy(), a["e_pins"].numpy(),
-                              a["v_off"].numpy(), a["v_edges"].numpy(),
-                              a["w"].numpy().view(np.uint32)) for g, a in pinned]
+    views, keep = served_pool(pool_count, vertex_side=not edge_side_only)
     gen_s = time.perf_counter() - t0
     arrivals = synth.gen.poisson_arrivals(2005, rate, duration)
     pick = np.random.Generator(np.random.PCG64(3005)).integers(0, len(views), size=arrivals.size)
@@ -279,7 +281,9 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
     srv.close()
     end = max(r["t_done"] for r in done)
     ok = [r for r in done if r["status"] == 0]
-    lat = np.array([r["t_done"] - sched[r["id"]] for r in ok if arrivals[r["id"]] >= min(warmup_s, 0.2 * duration)])
+    steady = [r for r in ok if arrivals[r["id"]] >= min(warmup_s, 0.2 * duration)]
+    lat = np.array([r["t_done"] - sched[r["id"]] for r in steady])
+    wait = np.array([r["t_admit"] - r["t_submit"] for r in steady])
     kap = sum(views[pick[r["id"]]].kappa for r in ok)
     return {"rate": rate, "duration_s": duration, "requests": int(arrivals.size),
             "completed": len(ok), "failed": len(done) - len(ok), "pool": pool_count,
@@ -290,7 +294,140 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
             "hypergraphs_per_s": len(ok) / (end - start),
             "incidences_per_s": kap / (end - start),
             "mean_wave": float(np.mean([r["wave_size"] for r in ok])),
+            "queue_wait_p50_ms": float(np.percentile(wait, 50) * 1e3),
+            "queue_wait_p99_ms": float(np.percentile(wait, 99) * 1e3),
+            "admission_stalls": int(info["stalls"]), "stall_s": float(info["stall_s"]),
             "arena_peak_gb": info["arena_peak"] / (1 << 30)}
+
+
+_POOL = {}
+
+
+def served_pool(count, vertex_side=False):
+    """The served workload's request pool in pinned host memory (asynchronous
+    uploads): kappa log-uniform in [1e3, 1e7], |e| ~ U{2..32}, m =
+    round(kappa/17), n = max(32, round(m/2)), w ~ U{1..1e6}, drawn in worker
+    processes; with vertex_side False only the edge side is drawn and sent.
+    Returns (views of the pinned arrays, the tensors that back them)."""
+    key = (count, vertex_side)
+    if key in _POOL:
+        return _POOL[key]
+    import numpy as np
+    import torch
+    import synth
+    pool = synth.config_served_pool(seed=1005, count=count, vertex_side=vertex_side,
+                                    processes=min(16, os.cpu_count() or 1))
+    keep, views = [], []
+    for g in pool:
+        arrs = {}
+        names = ("e_off", "e_pins", "v_off", "v_edges") if vertex_side else ("e_off", "e_pins")
+        for name in names:
+            t = torch.empty(getattr(g, name).size, dtype=torch.int32, pin_memory=True)
+            t.numpy()[:] = getattr(g, name)
+            arrs[name] = t
+        t = torch.empty(g.m, dtype=torch.int32, pin_memory=True)
+        t.numpy()[:] = g.w.view(np.int32)
+        arrs["w"] = t
+        keep.append(arrs)
+        empty = np.zeros(0, np.int32)
+        views.append(synth.Hypergraph(
+            g.n, g.m, arrs["e_off"].numpy(), arrs["e_pins"].numpy(),
+            arrs["v_off"].numpy() if vertex_side else empty,
+            arrs["v_edges"].numpy() if vertex_side else empty,
+            arrs["w"].numpy().view(np.uint32)))
+    _POOL[key] = (views, keep)
+    return views, keep
+
+
+def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s):
+    """Saturation throughput of the request server on the served workload's
+    pool: a closed loop keeps `inflight` requests submitted (request i draws
+    pool entry i mod pool, priority seed i) for `duration` s, counting the
+    completions after the first fifth; beside it the plain form, one request
+    at a time on the same sequence: upload of its edge side from the pinned
+    pool, hgm_match, bitmap back to the host, for `plain_s` s.  A sample of
+    the served bitmaps is compared with the plain form's."""
+    import numpy as np
+    import torch
+    import paper_2602_22976_amd as hgm
+    views, _ = served_pool(pool_count, vertex_side=False)
+    order = np.random.Generator(np.random.PCG64(4005)).permutation(len(views))
+    req = lambda i: views[order[i % len(views)]]
+    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"),
+                     edge_side_only=True)
+    t_start = time.monotonic()
+    nxt = 0
+    live = 0
+    done = []
+    while nxt < inflight:
+        srv.submit(req(nxt), nxt, req_id=nxt)
+        nxt += 1
+        live += 1
+    while live > 0:
+        res = srv.poll(cap=1024, timeout_s=0.05)
+        for r in res:
+            done.append((r, time.monotonic()))
+            live -= 1
+            if time.monotonic() - t_start < duration:
+                srv.submit(req(nxt), nxt, req_id=nxt)
+                nxt += 1
+                live += 1
+    info = srv.info()
+    srv.close()
+    t_end = max(t for _, t in done)
+    t_win = t_start + 0.2 * duration
+    win = [r for r, t in done if t >= t_win and r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in win])
+    kap = sum(req(r["id"]).kappa for r in win)
+    served = {r["id"]: r["bits"] for r, _ in done[:64]}
+
+    # Plain form on the same request sequence.
+    dev = "cuda:0"
+    big_m = max(g.m for g in views)
+    big_k = max(g.kappa for g in views)
+    d_off = torch.empty(big_m + 1, dtype=torch.int32, device=dev)
+    d_pins = torch.empty(big_k, dtype=torch.int32, device=dev)
+    d_w = torch.empty(big_m, dtype=torch.int32, device=dev)
+    d_bits = torch.empty((big_m + 31) // 32, dtype=torch.int32, device=dev)
+    opts = hgm.make_opts("auto")
+    wsz = max(hgm.hgm_workspace_size(hgm.DeviceHypergraph(
+        g.n, g.m, d_off[:g.m + 1], d_pins[:g.kappa], d_off[:0], d_pins[:0], d_w[:g.m]).csr(),
+        opts) for g in views)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    host_bits = torch.empty((big_m + 31) // 32, dtype=torch.int32, pin_memory=True)
+    _, keep = served_pool(pool_count, vertex_side=False)
+    mismatch = 0
+    n_plain = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < plain_s or n_plain < 8:
+        g = req(n_plain)
+        a = keep[order[n_plain % len(views)]]
+        d_off[:g.m + 1].copy_(a["e_off"], non_blocking=True)
+        d_pins[:g.kappa].copy_(a["e_pins"], non_blocking=True)
+        d_w[:g.m].copy_(a["w"], non_blocking=True)
+        dg = hgm.DeviceHypergraph(g.n, g.m, d_off[:g.m + 1], d_pins[:g.kappa], d_off[:0],
+                                  d_pins[:0], d_w[:g.m])
+        nw = (g.m + 31) // 32
+        hgm.match(dg, n_plain, opts, workspace=ws, bits=d_bits[:max(nw, 1)], want_stats=False)
+        host_bits[:nw].copy_(d_bits[:nw], non_blocking=True)
+        torch.cuda.synchronize()
+        if n_plain in served:
+            mismatch += int(not np.array_equal(host_bits[:nw].numpy().view(np.uint32),
+                                               served[n_plain]))
+        n_plain += 1
+    t_plain = time.perf_counter() - t0
+    cap = len(win) / (t_end - t_win)
+    plain = n_plain / t_plain
+    return {"pool": len(views), "inflight": inflight, "workers": workers,
+            "duration_s": duration, "completed": len(done),
+            "hypergraphs_per_s": cap, "incidences_per_s": kap / (t_end - t_win),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "admission_stalls": int(info["stalls"]),
+            "plain_hypergraphs_per_s": plain, "plain_requests": n_plain,
+            "served_over_plain": cap / plain,
+            "plain_mismatches_in_sample": mismatch}
 
 
 def cpu_model() -> str:
@@ -302,6 +439,29 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown CPU"
+
+
+def tuning_leg(reps=3):
+    """Default vs autotuned schedule (hgm_tune / hgm_tune_batch, median of
+    `reps` calls per candidate) on the power-law and hub-stress instances and
+    a 1,024-instance sample of the batched workload."""
+    import torch
+    import paper_2602_22976_amd as hgm
+    import synth
+    out = {}
+    for name, make in (("power-law", synth.config_power_law),
+                       ("hub", synth.config_hub_stress)):
+        dg = hgm.DeviceHypergraph.from_host(make(), "cuda:0")
+        best, rep = hgm.tune(dg, 1, hgm.make_opts("auto"), reps=reps)
+        out[name] = rep
+        del dg
+        torch.cuda.empty_cache()
+    db = hgm.DeviceBatch.from_host(synth.config_batched(seed=1004, count=1024), "cuda:0")
+    best, rep = hgm.tune_batch(db, hgm.make_opts("auto"), reps=reps)
+    out["batched_1024"] = rep
+    del db
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(g, seed, budget_s, sum_k, reseed=False):
@@ -379,7 +539,12 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="duration of the served leg (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--capacity-seconds", type=float, default=10.0,
+                    help="closed-loop saturation run of the server and plain form (0 = skip)")
+    ap.add_argument("--capacity-inflight", type=int, default=64)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="1: default vs autotuned schedules (power-law, hub, batched sample)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-workers", type=int, default=3)
     ap.add_argument("--serve-vertex-side", type=int, default=0,
@@ -532,6 +697,15 @@ def main():
         result["served"] = served_leg(args.serve_rate, args.serve_seconds, args.serve_pool,
                                       args.serve_budget_gb, args.serve_workers,
                                       edge_side_only=not args.serve_vertex_side)
+    if args.capacity_seconds > 0:
+        result["served_capacity"] = served_capacity(args.serve_pool, args.serve_budget_gb,
+                                                    args.serve_workers, args.capacity_inflight,
+                                                    args.capacity_seconds,
+                                                    max(2.0, args.capacity_seconds / 2))
+    if args.tune:
+        del ws
+        torch.cuda.empty_cache()
+        result["tuning"] = tuning_leg()
     if args.cpu_baseline > 0:
         result["cpu_baseline"] = cpu_baseline(g, seed, args.cpu_baseline, sum_k,
                                               bool(args.reseed))

@@ -350,6 +350,9 @@ typedef struct hgm_server_opts {
 typedef struct hgm_server_state {
     int64_t queued, submitted, completed;
     uint64_t arena_bytes, arena_used, arena_peak;  /* peak never exceeds arena_bytes */
+    int64_t stalls;          /* times a worker found requests queued but none fitting the
+                                free arena memory, and waited for memory to return */
+    double stall_s;          /* total time spent in those waits */
 } hgm_server_state;
 
 typedef struct hgm_server hgm_server;

@@ -89,7 +89,8 @@ class HgmServerOpts(ctypes.Structure):
 class HgmServerState(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int64), ("submitted", ctypes.c_int64),
                 ("completed", ctypes.c_int64), ("arena_bytes", ctypes.c_uint64),
-                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64)]
+                ("arena_used", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
+                ("stalls", ctypes.c_int64), ("stall_s", ctypes.c_double)]
 
 
 HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE, HGM_K_SOLO = range(6)

@@ -111,6 +111,8 @@ struct hgm_server {
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;  // one per worker
     int64_t submitted = 0, completed = 0;
+    int64_t stalls = 0;  // waits for arena memory with requests queued
+    double stall_s = 0;
 
     hgm_server(char *base, size_t bytes) : arena_base(base), arena(bytes) {}
 };
@@ -363,7 +365,10 @@ void worker_main(hgm_server *S, hipStream_t stream) {
                     if (S->arena.alloc(L.total, &off)) break;
                 }
                 // Nothing fits now: wait for memory to come back.
+                const double w0 = now_s();
                 S->cv_work.wait(lk);
+                S->stalls += 1;
+                S->stall_s += now_s() - w0;
                 if (S->stopping && S->queue.empty()) break;
             }
             if (wave.empty()) {
@@ -486,6 +491,8 @@ int hgm_server_info(hgm_server *S, hgm_server_state *st) {
     st->arena_bytes = S->arena.size();
     st->arena_used = S->arena.used();
     st->arena_peak = S->arena.peak();
+    st->stalls = S->stalls;
+    st->stall_s = S->stall_s;
     return HGM_OK;
 }
 

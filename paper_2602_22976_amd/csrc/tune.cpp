@@ -49,7 +49,7 @@ struct Knob {
 std::vector<Knob> knobs(bool batch) {
     std::vector<Knob> k = {
         {"solo", &hgm_opts::solo_max_kappa, {-1, 1 << 16, 1 << 18, 1 << 20, 1 << 22}, true},
-        {"grid", &hgm_opts::edge_grid, {512, 1024, 2048, 4096}, false},
+        {"grid", &hgm_opts::edge_grid, {512, 1024, 2048, 4096, 8192, 16384}, false},
         {"bpc", &hgm_opts::blocks_per_cu, {2, 4, 8, 16}, false},
         {"hub", &hgm_opts::hub_threshold, {1024, 4096, 8192, 32768, 1 << 30}, false},
         {"hot", &hgm_opts::hot_degree, {16, 64, 256}, false},
@@ -64,7 +64,7 @@ std::vector<Knob> knobs(bool batch) {
 
 // The candidates that need the most workspace: the largest edge grid (the
 // live lists), the lowest hub threshold (the hub pieces), a solo part.
-constexpr int32_t kMaxTunedGrid = 4096;
+constexpr int32_t kMaxTunedGrid = 16384;
 constexpr int32_t kMinTunedHub = 1024;
 
 hgm_opts largest_workspace(const hgm_opts *base) {

@@ -262,16 +262,47 @@ def config_batched(seed: int = 1004, count: int = 4096, n_lo: int = 100,
     return batch_from_instances(graphs, np.arange(count, dtype=np.uint32))
 
 
+def edge_side_instance(seed: int, n: int, m: int, smin: int = 2, smax: int = 32,
+                       wmin: int = 1, wmax: int = 1_000_000) -> Hypergraph:
+    """random_instance's edge side alone: the same sizes, distinct pins and
+    weights from the same seed, pins left in draw order (any order is valid)
+    and no vertex side (v_off, v_edges empty): requests that carry only the
+    edge side need no transpose."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    smax = min(smax, n)
+    smin = min(smin, smax)
+    sizes = rng.integers(smin, smax + 1, size=m).astype(np.int64)
+    off = _offsets(sizes)
+    pins = _draw_distinct(rng, sizes, off, lambda k: rng.integers(0, max(n, 1), size=k))
+    w = rng.integers(wmin, wmax + 1, size=m, dtype=np.uint64).astype(np.uint32)
+    return Hypergraph(n, m, off.astype(np.int32), pins.astype(np.int32),
+                      np.zeros(0, np.int32), np.zeros(0, np.int32), w)
+
+
+def _served_one(args):
+    sub, n, m, vertex_side = args
+    if vertex_side:
+        return random_instance(sub, n, m, 2, 32, 1, 1_000_000)
+    return edge_side_instance(sub, n, m, 2, 32, 1, 1_000_000)
+
+
 def config_served_pool(seed: int = 1005, count: int = 1024, k_lo: float = 1e3,
-                       k_hi: float = 1e7):
-    """Request pool: kappa log-uniform, |e| ~ U{2..32}, m = round(kappa/17)."""
+                       k_hi: float = 1e7, vertex_side: bool = True, processes: int = 1):
+    """Request pool: kappa log-uniform, |e| ~ U{2..32}, m = round(kappa/17),
+    n = max(32, round(m/2)), w ~ U{1..1e6}.  vertex_side=False draws only the
+    edge side (edge_side_instance, same sizes, pins and weights); processes >
+    1 draws the instances in that many worker processes (same result)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     kap = np.exp(rng.uniform(math.log(k_lo), math.log(k_hi), size=count))
     ms = np.maximum(1, np.rint(kap / 17.0)).astype(np.int64)
     ns = np.maximum(32, np.rint(ms / 2.0)).astype(np.int64)
     sub = rng.integers(0, 2 ** 63, size=count)
-    return [random_instance(int(sub[i]), int(ns[i]), int(ms[i]), 2, 32, 1, 1_000_000)
-            for i in range(count)]
+    jobs = [(int(sub[i]), int(ns[i]), int(ms[i]), vertex_side) for i in range(count)]
+    if processes <= 1:
+        return [_served_one(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(processes) as pool:
+        return pool.map(_served_one, jobs, chunksize=4)
 
 
 def poisson_arrivals(seed: int, rate: float, duration: float) -> np.ndarray:
