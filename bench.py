@@ -430,6 +430,78 @@ def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s)
             "plain_mismatches_in_sample": mismatch}
 
 
+def ceilings(grid_per_cu=8):
+    """Rates of the access patterns the round kernels use, each timed with HIP
+    events on torch's current stream (median of 5 launches after one): the
+    streaming read rate (1 GiB), random 8-byte and 1-byte gathers from
+    buffers of 2 MiB (an XCD's L2 holds it), 16 MiB (best[] of the power-law
+    workload) and 256 MiB (beyond the Infinity Cache), device-scope 64-bit
+    atomic max at random addresses (plain and filtered by a read, as the
+    scatter runs it) over 16 MiB, and on one address."""
+    import ctypes
+    import torch
+    from paper_2602_22976_amd import build as hb
+    if not os.path.exists(hb.PROBE_LIB):
+        hb.build(force=True)
+    lib = ctypes.CDLL(hb.PROBE_LIB)
+    P = ctypes.c_void_p
+    lib.hgm_probe_stream.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int]
+    lib.hgm_probe_gather.argtypes = [P, ctypes.c_int64, ctypes.c_int, P, ctypes.c_int64, P, P,
+                                     ctypes.c_int]
+    lib.hgm_probe_atomic.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int, P,
+                                     ctypes.c_int]
+    dev = "cuda:0"
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    grid = cus * grid_per_cu
+    stream = torch.cuda.current_stream().cuda_stream
+    sink = torch.zeros(4, dtype=torch.int32, device=dev)
+    count = 1 << 26
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    idx = torch.randint(0, 2 ** 31 - 1, (count,), dtype=torch.int64, device=dev,
+                        generator=gen).to(torch.int32)
+
+    def timed(launch):
+        launch()
+        times = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            launch()
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        times.sort()
+        return times[2]
+
+    out = {"grid": grid, "count": count}
+    big = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    ms = timed(lambda: lib.hgm_probe_stream(big.data_ptr(), big.numel(), sink.data_ptr(), stream,
+                                           grid))
+    out["stream_read_GBps"] = big.numel() / (ms * 1e-3) / 1e9
+    del big
+    for mib in (2, 16, 256):
+        buf = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+        for eb in (8, 1):
+            ms = timed(lambda: lib.hgm_probe_gather(buf.data_ptr(), buf.numel(), eb,
+                                                    idx.data_ptr(), count, sink.data_ptr(),
+                                                    stream, grid))
+            out[f"gather{eb}_{mib}MiB_G_per_s"] = count / (ms * 1e-3) / 1e9
+        del buf
+    buf = torch.zeros((16 << 20) // 8, dtype=torch.int64, device=dev)
+    for filt in (0, 1):
+        buf.zero_()
+        ms = timed(lambda: lib.hgm_probe_atomic(buf.data_ptr(), buf.numel(), idx.data_ptr(),
+                                                count, filt, stream, grid))
+        out[("filtered_" if filt else "") + "atomic_max8_16MiB_G_per_s"] = count / (ms * 1e-3) / 1e9
+    n1 = 1 << 20
+    ms = timed(lambda: lib.hgm_probe_atomic(buf.data_ptr(), 1, idx.data_ptr(), n1, 0, stream,
+                                            grid))
+    out["one_address_atomic_max8_G_per_s"] = n1 / (ms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -551,6 +623,9 @@ def main():
                     help="1: requests also upload the vertex side (default: edge side only)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
+    ap.add_argument("--ceilings", type=int, default=0,
+                    help="1: only measure the memory-system ceilings (streaming, random "
+                         "gathers, atomics) and print them as one JSON line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -567,6 +642,9 @@ def main():
         sys.exit(1)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.ceilings:
+        print(json.dumps({"ceilings": ceilings()}), flush=True)
         return
 
     import paper_2602_22976_amd as hgm

@@ -13,6 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhgm.so")
 SOURCES = ["kernels.hip", "api.hip", "server.cpp", "tune.cpp"]
+PROBE_SOURCE = "probe.hip"
 
 
 def hipcc() -> str:
@@ -30,7 +31,8 @@ def source_digest() -> str:
     """SHA-256 (first 16 hex digits) over the library's sources, the headers
     they include and the compiler flags."""
     h = hashlib.sha256()
-    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    files = sorted(f for f in os.listdir(CSRC)
+                   if f.endswith((".hip", ".cpp", ".h")) and f != PROBE_SOURCE)
     for fn in files:
         h.update(fn.encode())
         with open(os.path.join(CSRC, fn), "rb") as f:
@@ -47,11 +49,20 @@ def command(out: str):
            [os.path.join(CSRC, s) for s in SOURCES]
 
 
+# Memory-system probes (bench.py --ceilings): their own library, not linked
+# into libhgm.so.
+PROBE_LIB = os.path.join(HERE, "libhgm_probe.so")
+
+
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
         subprocess.check_call(command(tmp))
         os.replace(tmp, LIB)
+    if force or not os.path.exists(PROBE_LIB):
+        tmp = PROBE_LIB + ".tmp"
+        subprocess.check_call([hipcc()] + FLAGS + ["-o", tmp, os.path.join(CSRC, PROBE_SOURCE)])
+        os.replace(tmp, PROBE_LIB)
     return LIB
 
 
