@@ -63,7 +63,7 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(stats, variant_rounds, n, pairs=False, reseed=False):
+def algorithmic_bytes(stats, variant_rounds, n, pairs=False, reseed=False, tail_from=None):
     """Bytes each kernel class must move, from the per-round counts.
 
     Units per round r: E = live edges, K = their pins, M / P = matched edges
@@ -94,16 +94,30 @@ def algorithmic_bytes(stats, variant_rounds, n, pairs=False, reseed=False):
               length read and write), per listed incidence id 4 + live key 8
               (the pins live one round earlier, an upper bound since done
               vertices are skipped), per kept incidence 4
+      tail:   rounds from `tail_from` on run in the one-workgroup tail,
+              whose compact list slots hold id 4 + pin offset and count (or
+              two pins) 8 + key 8: at takeover the list is gathered (20 B
+              read and 20 B written per live edge); per round the test reads
+              each slot (20 B), per pin 4 + best 8, per matched edge 4, per
+              matched pin 1; the retire reads each slot again, per pin 4 +
+              done 1, writes 20 B per survivor, and forms the next maximum
+              with 16 B per surviving pin (a zero, then the atomic)
     """
     E = list(stats["live_edges"]) + [0]
     K = list(stats["live_pins"]) + [0]
     M = stats["matched_per_round"]
     P = stats["matched_pins"]
     R = stats["rounds"]
-    out = {"scatter": 0.0, "test": 0.0, "retire": 0.0, "vertex_max": 0.0}
+    out = {"scatter": 0.0, "test": 0.0, "retire": 0.0, "vertex_max": 0.0, "tail": 0.0}
     offb = 0 if pairs else 8   # e_off[e], e_off[e + 1] per edge (record: offset, count)
     recw = 8 + 8 if pairs else 12 + 8   # record written per survivor, key included
     for r in range(R):
+        if tail_from is not None and r >= tail_from:
+            if r == tail_from:
+                out["tail"] += 40 * E[r]
+            out["tail"] += (20 * E[r] + 12 * K[r] + 4 * M[r] + P[r]) + \
+                           (20 * E[r] + 5 * K[r] + 20 * E[r + 1] + 16 * K[r + 1])
+            continue
         crew_r = variant_rounds(r)
         crew_next = variant_rounds(r + 1)
         if r == 0 and not crew_r:
@@ -711,8 +725,10 @@ def main():
 
     crew_all = args.variant == "crew"
     crew0 = crew_all or launches.get("vertex_max", 0) > 0   # AUTO's round-0 form
+    tail_from = (int(round(launches.get("test", 0) / args.steps))
+                 if launches.get("tail", 0) > 0 else None)
     model = algorithmic_bytes(st, lambda r: crew_all or (r == 0 and crew0), g.n, pairs,
-                              bool(args.reseed))
+                              bool(args.reseed), tail_from)
     cand = {k: tot_ms[k] for k in model if tot_ms.get(k, 0) > 0}
     dom = max(cand, key=cand.get)
     dom_ms = tot_ms[dom] / args.steps

@@ -136,6 +136,10 @@ typedef struct hgm_opts {
     int32_t first_batch_pct; /* rounds enqueued before the first termination
                                 check: pct / 100 * log2(kappa) (default 40,
                                 35 for graphs; at most 400) */
+    int32_t tail_pins;       /* hgm_match: once a round has at most this many
+                                live pins (and at most 65536 live edges), one
+                                workgroup runs every remaining round
+                                (0 = library default: never; -1 = never) */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */
@@ -145,7 +149,8 @@ typedef struct hgm_opts {
 #define HGM_K_TEST 3       /* local-max test and marking */
 #define HGM_K_RETIRE 4     /* retire + live-list compaction (+ next maximum in CRCW) */
 #define HGM_K_SOLO 5       /* batches: every round of the instances matched by one workgroup */
-#define HGM_K_CLASSES 6
+#define HGM_K_TAIL 6       /* one instance: the remaining rounds run by one workgroup */
+#define HGM_K_CLASSES 7
 
 /* Optional statistics (host memory).  The arrays may be NULL; when given they
  * hold `cap` entries and receive, for round r < cap: the number of live edges

@@ -52,10 +52,10 @@ class HgmOpts(ctypes.Structure):
                 ("pairs", ctypes.c_int32), ("solo_max_kappa", ctypes.c_int32),
                 ("edge_grid", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("clear_ratio", ctypes.c_int32), ("hot_degree", ctypes.c_int32),
-                ("first_batch_pct", ctypes.c_int32)]
+                ("first_batch_pct", ctypes.c_int32), ("tail_pins", ctypes.c_int32)]
 
 SCHEDULE_FIELDS = ["hub_threshold", "solo_max_kappa", "edge_grid", "blocks_per_cu",
-                   "clear_ratio", "hot_degree", "first_batch_pct"]
+                   "clear_ratio", "hot_degree", "first_batch_pct", "tail_pins"]
 
 
 class HgmBatch(ctypes.Structure):
@@ -93,9 +93,10 @@ class HgmServerState(ctypes.Structure):
                 ("stalls", ctypes.c_int64), ("stall_s", ctypes.c_double)]
 
 
-HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE, HGM_K_SOLO = range(6)
-HGM_K_CLASSES = 6
-KERNEL_CLASS_NAMES = ["setup", "scatter", "vertex_max", "test", "retire", "solo"]
+(HGM_K_SETUP, HGM_K_SCATTER, HGM_K_VERTEX_MAX, HGM_K_TEST, HGM_K_RETIRE, HGM_K_SOLO,
+ HGM_K_TAIL) = range(7)
+HGM_K_CLASSES = 7
+KERNEL_CLASS_NAMES = ["setup", "scatter", "vertex_max", "test", "retire", "solo", "tail"]
 
 
 class HgmStats(ctypes.Structure):
@@ -329,7 +330,8 @@ class DeviceBatch:
 
 def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False,
               max_rounds=0, reseed=False, pairs=False, solo_max_kappa=0, edge_grid=0,
-              blocks_per_cu=0, clear_ratio=0, hot_degree=0, first_batch_pct=0) -> HgmOpts:
+              blocks_per_cu=0, clear_ratio=0, hot_degree=0, first_batch_pct=0,
+              tail_pins=0) -> HgmOpts:
     o = HgmOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.hub_threshold = hub_threshold
@@ -341,6 +343,7 @@ def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False
     o.solo_max_kappa = solo_max_kappa
     o.edge_grid, o.blocks_per_cu, o.clear_ratio = edge_grid, blocks_per_cu, clear_ratio
     o.hot_degree, o.first_batch_pct = hot_degree, first_batch_pct
+    o.tail_pins = tail_pins
     return o
 
 

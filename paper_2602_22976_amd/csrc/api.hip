@@ -40,6 +40,14 @@ constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
 // Rounds of per-round sums the solo part records (later rounds of a solo
 // instance count in the totals only).
 constexpr int kSoloRounds = 1 << 16;
+// One instance: the tail workgroup takes over a round with at most this many
+// live pins (and at most kTailCap live edges).  Off unless asked for: on the
+// synthetic workloads a round in one workgroup costs as much as a round of
+// the grid-wide kernels (both are a chain of dependent memory accesses).
+constexpr int kDefaultTailPins = -1;
+constexpr int kTailCap = 1 << 16;
+// Rows of the tail record copied with the round counters at each check.
+constexpr int kTailRowsFirst = 64;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -47,8 +55,9 @@ struct Layout {
     bool stored_keys;  // batch: keys precomputed per instance
     size_t key, eseed, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
-        piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, solo, total;
-    int ring, grid, region, piece_cap, solo_rounds;
+        piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, solo, tail_list[2][4],
+        tail, total;
+    int ring, grid, region, piece_cap, solo_rounds, tail_cap;
 };
 
 // Edge schedule: `grid` workgroups, each owning `region` consecutive edge ids
@@ -64,6 +73,7 @@ struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
     int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part)
     int edge_grid, blocks_per_cu, clear_ratio, hot_degree, first_batch_pct;  // 0 = per kind
+    int64_t tail_pins;  // one instance: tail bound (-1: no tail)
     bool reseed;            // priorities redrawn every round (round_seed)
     bool pairs;             // graph: two pins per edge at e_pins[2e], no offsets
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
@@ -101,6 +111,8 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     o->clear_ratio = d.clear_ratio ? d.clear_ratio : kFullClearRatio;
     o->hot_degree = d.hot_degree ? d.hot_degree : kHotDegree;
     o->first_batch_pct = d.first_batch_pct;  // 0: resolved per instance (graphs differ)
+    if (d.tail_pins < -1) return HGM_E_ARG;
+    o->tail_pins = d.tail_pins == 0 ? kDefaultTailPins : d.tail_pins;
     return HGM_OK;
 }
 
@@ -176,6 +188,14 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
                         ? (int)std::min<int64_t>(kSoloRounds, std::max<int64_t>(m, 1))
                         : 0;
     L.solo = take(L.solo_rounds ? 8 * ((size_t)kSoloHeader + 5 * (size_t)L.solo_rounds) : 0);
+    // One instance: the tail's compact lists (id, pin offset or first pin,
+    // count or second pin, key; two buffers) and its record.
+    L.tail_cap = !batch && o.tail_pins > 0 ? (int)std::min<int64_t>(kTailCap, std::max<int64_t>(m, 1))
+                                           : 0;
+    for (int k = 0; k < 2; ++k)
+        for (int f = 0; f < 4; ++f)
+            L.tail_list[k][f] = take((f == 3 ? 8 : 4) * (size_t)L.tail_cap);
+    L.tail = take(L.tail_cap ? 8 * ((size_t)kTailHeader + 5 * ((size_t)L.tail_cap + 2)) : 0);
     L.total = at;
     return L;
 }
@@ -221,6 +241,15 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.explicit0 = L.solo_rounds > 0;
     s.solo = L.solo_rounds ? (unsigned long long *)(b + L.solo) : nullptr;
     s.solo_rounds = L.solo_rounds;
+    for (int k = 0; k < 2; ++k) {
+        s.tail_e[k] = (int32_t *)(b + L.tail_list[k][0]);
+        s.tail_a[k] = (int32_t *)(b + L.tail_list[k][1]);
+        s.tail_b[k] = (int32_t *)(b + L.tail_list[k][2]);
+        s.tail_key[k] = (uint64_t *)(b + L.tail_list[k][3]);
+    }
+    s.tail = L.tail_cap ? (unsigned long long *)(b + L.tail) : nullptr;
+    s.tail_cap = L.tail_cap;
+    s.tail_pins = o.tail_pins;
     return s;
 }
 
@@ -544,11 +573,18 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
         return last * std::pow(f, (double)(r - (known - 1)));
     };
     int launched = 0;  // rounds whose test has been enqueued
+    // The tail workgroup (one instance): launched after the retire pass of a
+    // round the host expects to have at most tail_pins live pins, which then
+    // ends the batch of rounds; once a launch found more, later ones do not.
+    const bool tail_on = s.tail != nullptr;
+    bool tail_missed = false;
+    std::vector<unsigned long long> tail_head(kTailHeader + 5 * (size_t)kTailRowsFirst, 0);
     while (!finished) {
         int batch = next_batch(o, launched, live_p, g.kappa == 2 * (int64_t)g.m);
         if (o.max_rounds > 0) batch = std::min(batch, o.max_rounds - launched);
         if (batch <= 0) return HGM_E_ROUND_LIMIT;
         const int first = launched;
+        bool tail_launched = false;
         HGM_TRY(T.resume());
         for (int b = 0; b < batch; ++b) {
             const int r = launched;
@@ -567,6 +603,13 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                 HGM_TRY(T.after(HGM_K_VERTEX_MAX, r + 1));
             }
             launched += 1;
+            if (tail_on && predicted_pins(r + 1) <= (double)o.tail_pins) {
+                HGM_TRY(launch_tail(L, g, s, r + 1, matched_bits, seed, o.reseed ? 1 : 0,
+                                    o.max_rounds));
+                HGM_TRY(T.after(HGM_K_TAIL, r + 1));
+                tail_launched = true;
+                if (!tail_missed) break;
+            }
         }
         // Copy the slots of rounds first .. launched (at most two ranges of the ring).
         for (int r = first; r <= launched;) {
@@ -579,6 +622,10 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
         if (explicit0 && first == 0)
             HGM_TRY(hipMemcpyAsync(solo_head.data(), s.solo,
                                    sizeof(unsigned long long) * solo_head.size(),
+                                   hipMemcpyDeviceToHost, L.stream));
+        if (tail_launched)
+            HGM_TRY(hipMemcpyAsync(tail_head.data(), s.tail,
+                                   sizeof(unsigned long long) * tail_head.size(),
                                    hipMemcpyDeviceToHost, L.stream));
         HGM_TRY(hipStreamSynchronize(L.stream));
         auto sum = [](const unsigned long long *a) {
@@ -597,7 +644,12 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                 launched = first;
             }
         }
-        for (int r = first; r < launched; ++r) {
+        // A tail that took over at round t0 ran rounds t0 onwards: the ring
+        // holds the rounds before it.
+        const bool tail_taken = tail_launched && tail_head[0] != 0;
+        if (tail_launched && !tail_taken) tail_missed = true;
+        const int ring_end = tail_taken ? std::min(launched, (int)tail_head[0] - 1) : launched;
+        for (int r = first; r < ring_end; ++r) {
             const RoundStats &cur = ring[r % lay.ring];
             const RoundStats &nxt = ring[(r + 1) % lay.ring];
             matched_r.push_back((int64_t)sum(cur.matched));
@@ -611,6 +663,34 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
             }
             live_e.push_back((int64_t)live_next);
             live_p.push_back((int64_t)sum(nxt.kappa));
+        }
+        if (tail_taken) {
+            // Rounds t0 .. end - 1 ran in the tail; its record holds their counts.
+            const int t0 = (int)tail_head[0] - 1, end = (int)tail_head[1];
+            const int nrows = end - t0;
+            std::vector<unsigned long long> row(5 * (size_t)std::max(nrows, 0));
+            if (nrows > kTailRowsFirst) {
+                HGM_TRY(hipMemcpyAsync(row.data(), s.tail + kTailHeader,
+                                       sizeof(unsigned long long) * row.size(),
+                                       hipMemcpyDeviceToHost, L.stream));
+                HGM_TRY(hipStreamSynchronize(L.stream));
+            } else if (nrows > 0) {
+                std::copy(tail_head.begin() + kTailHeader,
+                          tail_head.begin() + kTailHeader + 5 * (size_t)nrows, row.begin());
+            }
+            for (int j = 0; j < nrows; ++j) {
+                if (j > 0) {  // round t0's live counts came from the ring
+                    live_e.push_back((int64_t)row[5 * j + 0]);
+                    live_p.push_back((int64_t)row[5 * j + 1]);
+                }
+                matched_r.push_back((int64_t)row[5 * j + 2]);
+                weight_r.push_back(row[5 * j + 3]);
+                matched_p.push_back((int64_t)row[5 * j + 4]);
+            }
+            if (tail_head[2] == 1) return HGM_E_ROUND_LIMIT;
+            if (tail_head[2]) return HGM_E_HIP;  // the tail's round bound was exceeded
+            finished = true;
+            rounds = end;
         }
         if (max0_event >= 0 && T.on && max0_event < (int)T.cls.size()) {
             T.cls[max0_event] = ring[0].form == 1 ? HGM_K_SCATTER : HGM_K_VERTEX_MAX;

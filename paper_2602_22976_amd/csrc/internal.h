@@ -145,7 +145,24 @@ struct State {
     unsigned long long *solo;  // [kSoloHeader + 5 * solo_rounds] per-round sums of the solo
                                // instances (see SoloArgs); NULL without a solo part
     int32_t solo_rounds;       // rows of per-round sums
+    // Tail of one instance (k_tail): a compact live list, double-buffered,
+    // with each edge's pin offset and count (pair layout: its two pins) and
+    // key; and the tail's record (see kTailHeader).  tail_cap = 0: no tail.
+    int32_t *tail_e[2], *tail_a[2], *tail_b[2];
+    uint64_t *tail_key[2];
+    unsigned long long *tail;
+    int32_t tail_cap;          // live edges the tail takes at most
+    int64_t tail_pins;         // it takes over a round with at most this many live pins
 };
+
+// Tail record: word 0 = 1 + the round the tail took over at (0: not taken),
+// word 1 = the rounds of the whole matching when it finished, word 2 =
+// 1 when max_rounds stopped it with live edges (2: it ran more rounds than it
+// had live edges, which a correct maximum never does); then row j holds live
+// edges, live pins, matched edges, their weight and their pins of round
+// (taken round + j).
+constexpr int kTailHeader = 8;
+constexpr int kTailThreads = 1024;
 
 // Solo part of a batch: instances with at most max_kappa pins and at most
 // max_verts vertices are matched whole by one workgroup each (k_solo), every
@@ -214,5 +231,10 @@ hipError_t launch_max0(const Launch &L, const Graph &g, const State &s, uint32_t
 constexpr int kClearNone = 0, kClearAll = 1, kClearPins = 2;
 hipError_t launch_test(const Launch &L, const Graph &g, const State &s, int round, int clear,
                        uint32_t *bits, uint32_t kseed);
+// One workgroup checks round `round`'s live counts and, when they are within
+// the tail's bounds, runs every remaining round of the instance (one
+// instance, offset or pair layout; seed and reseed as for the other kernels).
+hipError_t launch_tail(const Launch &L, const Graph &g, const State &s, int round,
+                       uint32_t *bits, uint32_t seed, int reseed, int max_rounds);
 
 }  // namespace hgm

@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
         *s.piece_count = 0;
     }
     if (s.solo && threadIdx.x < kSoloHeader) s.solo[threadIdx.x] = 0;
+    if (s.tail && threadIdx.x < kTailHeader) s.tail[threadIdx.x] = 0;
     if (threadIdx.x < kSub) {
         s.hot[threadIdx.x] = 0;
         s.wrange[2 * threadIdx.x] = 0xFFFFFFFFu;
@@ -1657,6 +1658,244 @@ __global__ void __launch_bounds__(kBlock) k_live0_place(Graph g, State s, SoloAr
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tail of one instance.  Late rounds have few live edges, and three
+// grid-wide launches per round then cost far more than their work.  After
+// the retire pass of round R, one workgroup reads R's live counts; when
+// they are within the tail's bounds it gathers every workgroup's live list
+// (with its records) into one compact list, empties the lists so that the
+// rounds still enqueued after it find nothing to do, and runs rounds R,
+// R + 1, ... itself until no live edge remains (or max_rounds is reached):
+//   test    a live edge whose key equals best at every pin is matched; its
+//           bit is set and its pins marked done
+//   retire  every other live edge with a done pin leaves; the survivors
+//           are compacted into the other list with their next-round key
+//   max     best of the next round: zero at the survivors' pins, then each
+//           survivor raises it at its pins
+// best[R & 1] already holds round R's maximum (the retire pass of R built
+// it).  Counters of each round go to the tail record.  Each lane handles
+// kTailU list slots per step, their loads issued together.
+constexpr int kTailWaves = kTailThreads / kWave;
+constexpr int kTailU = 8;
+
+__device__ __forceinline__ int tail_exclusive_sum(int v, int *wave_tmp, int *total) {
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int incl = wave_inclusive_sum(v);
+    if (lane == kWave - 1) wave_tmp[wid] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kTailWaves; ++i) {
+        const int x = wave_tmp[i];
+        off += (i < wid) ? x : 0;
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return off + incl - v;
+}
+
+__device__ __forceinline__ unsigned long long tail_sum(unsigned long long v,
+                                                       unsigned long long *tmp) {
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if (lane == 0) tmp[wid] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int i = 0; i < kTailWaves; ++i) t += tmp[i];
+    __syncthreads();
+    return t;
+}
+
+// Pin k of a tail slot: pair layout (a, b) are the two pins; offset layout
+// a = pin offset, b = count.
+__device__ __forceinline__ int tail_pin(const Graph &g, int a, int b, int k) {
+    return g.pairs ? (k == 0 ? a : b) : g.e_pins[a + k];
+}
+
+__device__ __forceinline__ int tail_len(const Graph &g, int b) { return g.pairs ? 2 : b; }
+
+__global__ void __launch_bounds__(kTailThreads) k_tail(Graph g, State s, int round,
+                                                       uint32_t *bits, uint32_t seed,
+                                                       int reseed, int max_rounds) {
+    __shared__ int wave_tmp[kTailWaves];
+    __shared__ unsigned long long sum_tmp[kTailWaves];
+    __shared__ int take;
+    const int tid = threadIdx.x;
+    if (s.tail[0] != 0) return;  // an earlier launch took over (uniform read)
+    if (tid < kWave) {
+        const RoundStats &st = s.stats[round % s.ring];
+        unsigned long long live = st.live[tid], kap = st.kappa[tid];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            live += __shfl_xor(live, o, kWave);
+            kap += __shfl_xor(kap, o, kWave);
+        }
+        if (tid == 0)
+            take = live > 0 && live <= (unsigned long long)s.tail_cap &&
+                   kap <= (unsigned long long)s.tail_pins;
+    }
+    __syncthreads();
+    if (!take || (max_rounds > 0 && round >= max_rounds)) return;
+    // Gather the workgroups' live lists of `round` into tail list 0.
+    const int k = round & 1;
+    int E = 0;
+    unsigned long long K = 0;
+    for (int c0 = 0; c0 < s.grid; c0 += kTailThreads) {
+        const int b = c0 + tid;
+        const int n = b < s.grid ? s.cnt[k][b] : 0;
+        int total;
+        const int at = E + tail_exclusive_sum(n, wave_tmp, &total);
+        for (int i = 0; i < n; ++i) {
+            const int64_t src = (int64_t)b * s.region + i;
+            s.tail_e[0][at + i] = s.list[k][src];
+            s.tail_a[0][at + i] = s.rec_a[k][src];
+            s.tail_b[0][at + i] = s.rec_b[k][src];
+            s.tail_key[0][at + i] = s.rec_key[k][src];
+            K += (unsigned long long)tail_len(g, s.rec_b[k][src]);
+        }
+        if (b < s.grid) {
+            s.cnt[k][b] = 0;
+            s.cnt[k ^ 1][b] = 0;
+        }
+        E += total;
+    }
+    K = tail_sum(K, sum_tmp);
+    __syncthreads();  // the gathered list is complete
+    const int e0 = E;  // every round matches at least its largest live edge
+    int r = round, p = 0;
+    unsigned long long *rows = s.tail + kTailHeader;
+    for (;;) {
+        const uint64_t *best = s.best[r & 1];
+        // ---- test
+        unsigned long long nm = 0, wm = 0, pm = 0;
+        for (int j0 = tid; j0 < E; j0 += kTailU * kTailThreads) {
+            int a[kTailU], bb[kTailU], e[kTailU], pin0[kTailU];
+            uint64_t key[kTailU], bv[kTailU];
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u) {
+                const int j = j0 + u * kTailThreads;
+                const bool v = j < E;
+                e[u] = v ? s.tail_e[p][j] : -1;
+                a[u] = v ? s.tail_a[p][j] : 0;
+                bb[u] = v ? s.tail_b[p][j] : 0;
+                key[u] = v ? s.tail_key[p][j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u)
+                pin0[u] = (e[u] >= 0 && tail_len(g, bb[u]) > 0) ? tail_pin(g, a[u], bb[u], 0) : -1;
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u)
+                bv[u] = pin0[u] >= 0 ? __hip_atomic_load(&best[pin0[u]], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)
+                                     : key[u];
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u) {
+                if (e[u] < 0) continue;
+                const int len = tail_len(g, bb[u]);
+                bool ok = bv[u] == key[u];
+                for (int q = 1; q < len && ok; ++q)
+                    ok = __hip_atomic_load(&best[tail_pin(g, a[u], bb[u], q)], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP) == key[u];
+                if (!ok) continue;
+                atomicOr(&bits[e[u] >> 5], 1u << (e[u] & 31));
+                nm += 1;
+                wm += key[u] >> 32;
+                pm += (unsigned long long)len;
+                for (int q = 0; q < len; ++q) s.done[tail_pin(g, a[u], bb[u], q)] = 1;
+            }
+        }
+        nm = tail_sum(nm, sum_tmp);
+        wm = tail_sum(wm, sum_tmp);
+        pm = tail_sum(pm, sum_tmp);
+        if (tid == 0) {
+            unsigned long long *row = rows + 5 * (int64_t)(r - round);
+            row[0] = (unsigned long long)E;
+            row[1] = K;
+            row[2] = nm;
+            row[3] = wm;
+            row[4] = pm;
+        }
+        // ---- retire and compaction (the done marks are complete: the sums
+        // above end with a barrier)
+        const int rn = r + 1;
+        const uint32_t kseed_next = reseed ? round_seed(seed, rn) : seed;
+        int kept = 0;
+        unsigned long long kn = 0;
+        for (int c0 = 0; c0 < E; c0 += kTailU * kTailThreads) {
+            int a[kTailU], bb[kTailU], e[kTailU];
+            uint64_t key[kTailU];
+            bool alive[kTailU];
+            int mine = 0;
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u) {
+                const int j = c0 + tid * kTailU + u;  // lane-contiguous slots: kept in order
+                const bool v = j < E;
+                e[u] = v ? s.tail_e[p][j] : -1;
+                a[u] = v ? s.tail_a[p][j] : 0;
+                bb[u] = v ? s.tail_b[p][j] : 0;
+                key[u] = v ? s.tail_key[p][j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u) {
+                const int len = e[u] >= 0 ? tail_len(g, bb[u]) : 0;
+                bool dead = e[u] < 0 || len == 0;  // an empty edge was matched by its test
+                for (int q = 0; q < len && !dead; ++q) dead = s.done[tail_pin(g, a[u], bb[u], q)] != 0;
+                alive[u] = !dead;
+                mine += alive[u] ? 1 : 0;
+            }
+            int total;
+            int at = kept + tail_exclusive_sum(mine, wave_tmp, &total);
+#pragma unroll
+            for (int u = 0; u < kTailU; ++u) {
+                if (!alive[u]) continue;
+                s.tail_e[p ^ 1][at] = e[u];
+                s.tail_a[p ^ 1][at] = a[u];
+                s.tail_b[p ^ 1][at] = bb[u];
+                s.tail_key[p ^ 1][at] =
+                    reseed ? edge_key<false>(g, s, kseed_next, e[u]) : key[u];
+                kn += (unsigned long long)tail_len(g, bb[u]);
+                ++at;
+            }
+            kept += total;
+        }
+        K = tail_sum(kn, sum_tmp);  // ends with a barrier: the new list is complete
+        E = kept;
+        r = rn;
+        p ^= 1;
+        if (E == 0) break;
+        if (max_rounds > 0 && r >= max_rounds) {
+            if (tid == 0) s.tail[2] = 1;
+            break;
+        }
+        if (r - round >= e0) {  // cannot happen with a correct maximum: stop, reported
+            if (tid == 0) s.tail[2] = 2;
+            break;
+        }
+        // ---- the next round's maximum: zero at the survivors' pins, then raise
+        uint64_t *nb = s.best[r & 1];
+        for (int j = tid; j < E; j += kTailThreads) {
+            const int a = s.tail_a[p][j], bb = s.tail_b[p][j], len = tail_len(g, bb);
+            for (int q = 0; q < len; ++q) nb[tail_pin(g, a, bb, q)] = 0;
+        }
+        __syncthreads();
+        for (int j = tid; j < E; j += kTailThreads) {
+            const int a = s.tail_a[p][j], bb = s.tail_b[p][j], len = tail_len(g, bb);
+            const uint64_t key = s.tail_key[p][j];
+            for (int q = 0; q < len; ++q)
+                __hip_atomic_fetch_max(&nb[tail_pin(g, a, bb, q)], key, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        s.tail[1] = (unsigned long long)r;
+        s.tail[0] = (unsigned long long)round + 1;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_zero_words(uint32_t *p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
@@ -1696,6 +1935,13 @@ hipError_t launch_solo(const Launch &L, const Graph &g, const State &s, const So
 hipError_t launch_live0(const Launch &L, const Graph &g, const State &s, const SoloArgs &a) {
     hipLaunchKernelGGL(k_live0_count, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, a);
     hipLaunchKernelGGL(k_live0_place, dim3(s.grid), dim3(kBlock), 0, L.stream, g, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail(const Launch &L, const Graph &g, const State &s, int round,
+                       uint32_t *bits, uint32_t seed, int reseed, int max_rounds) {
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(kTailThreads), 0, L.stream, g, s, round, bits, seed,
+                       reseed, max_rounds);
     return hipGetLastError();
 }
 

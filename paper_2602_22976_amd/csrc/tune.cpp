@@ -43,37 +43,38 @@ struct Knob {
     const char *name;
     int32_t hgm_opts::*field;
     std::vector<int32_t> values;  // candidates (0 = library default)
-    bool batch_only;
+    int kind;                     // 0: both, 1: batches only, 2: one instance only
 };
 
 std::vector<Knob> knobs(bool batch) {
     std::vector<Knob> k = {
-        {"solo", &hgm_opts::solo_max_kappa, {-1, 1 << 16, 1 << 18, 1 << 20, 1 << 22}, true},
-        {"grid", &hgm_opts::edge_grid, {512, 1024, 2048, 4096, 8192, 16384}, false},
-        {"bpc", &hgm_opts::blocks_per_cu, {2, 4, 8, 16}, false},
-        {"hub", &hgm_opts::hub_threshold, {1024, 4096, 8192, 32768, 1 << 30}, false},
-        {"hot", &hgm_opts::hot_degree, {16, 64, 256}, false},
-        {"clear", &hgm_opts::clear_ratio, {2, 8, 32}, false},
-        {"first", &hgm_opts::first_batch_pct, {25, 40, 55}, false},
+        {"solo", &hgm_opts::solo_max_kappa, {-1, 1 << 16, 1 << 18, 1 << 20, 1 << 22}, 1},
+        {"grid", &hgm_opts::edge_grid, {512, 1024, 2048, 4096, 8192, 16384}, 0},
+        {"bpc", &hgm_opts::blocks_per_cu, {2, 4, 8, 16}, 0},
+        {"hub", &hgm_opts::hub_threshold, {1024, 4096, 8192, 32768, 1 << 30}, 0},
+        {"hot", &hgm_opts::hot_degree, {16, 64, 256}, 0},
+        {"clear", &hgm_opts::clear_ratio, {2, 8, 32}, 0},
+        {"first", &hgm_opts::first_batch_pct, {25, 40, 55}, 0},
+        {"tail", &hgm_opts::tail_pins, {-1, 1024, 4096, 32768}, 2},
     };
     std::vector<Knob> out;
     for (auto &x : k)
-        if (batch || !x.batch_only) out.push_back(x);
+        if (x.kind == 0 || x.kind == (batch ? 1 : 2)) out.push_back(x);
     return out;
 }
 
-// The candidates that need the most workspace: the largest edge grid (the
-// live lists), the lowest hub threshold (the hub pieces), a solo part.
-constexpr int32_t kMaxTunedGrid = 16384;
+// Fields at the candidates that need the most workspace: the lowest hub
+// threshold (the hub pieces), a solo part and a tail; every edge grid is
+// sized separately (largest_size).
 constexpr int32_t kMinTunedHub = 1024;
 
 hgm_opts largest_workspace(const hgm_opts *base) {
     hgm_opts o;
     memset(&o, 0, sizeof(o));
     if (base) o = *base;
-    o.edge_grid = std::max(o.edge_grid, kMaxTunedGrid);
     o.hub_threshold = o.hub_threshold ? std::min(o.hub_threshold, kMinTunedHub) : kMinTunedHub;
     if (o.solo_max_kappa < 0) o.solo_max_kappa = 0;
+    if (o.tail_pins <= 0) o.tail_pins = 32768;
     return o;
 }
 
@@ -86,6 +87,7 @@ int32_t default_of(const char *name, bool graph) {
     if (!strcmp(name, "hot")) return 64;
     if (!strcmp(name, "clear")) return 8;
     if (!strcmp(name, "first")) return graph ? 35 : 40;
+    if (!strcmp(name, "tail")) return -1;
     return 0;
 }
 
@@ -262,22 +264,37 @@ struct BitsCheck {
     }
 };
 
+// The largest workspace any candidate needs: the list capacity is not
+// monotone in the edge grid (it rounds the edges per workgroup up to whole
+// chunks), so every candidate grid is sized.
+template <typename F>
+size_t largest_size(const hgm_opts *base, bool batch, F size_of) {
+    size_t best = size_of(base);
+    if (!best) return 0;
+    hgm_opts o = largest_workspace(base);
+    for (auto &k : knobs(batch)) {
+        if (strcmp(k.name, "grid")) continue;
+        for (int32_t v : k.values) {
+            o.edge_grid = v;
+            const size_t x = size_of(&o);
+            if (!x) return 0;
+            best = std::max(best, x);
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t hgm_tune_workspace_size(const hgm_csr *g, const hgm_opts *base) {
-    const hgm_opts o = largest_workspace(base);
-    const size_t a = hgm_workspace_size(g, &o);
-    const size_t b = hgm_workspace_size(g, base);
-    return a && b ? std::max(a, b) : 0;
+    return largest_size(base, false, [&](const hgm_opts *o) { return hgm_workspace_size(g, o); });
 }
 
 size_t hgm_tune_batch_workspace_size(const hgm_batch *b, const hgm_opts *base) {
-    const hgm_opts o = largest_workspace(base);
-    const size_t x = hgm_batch_workspace_size(b, &o);
-    const size_t y = hgm_batch_workspace_size(b, base);
-    return x && y ? std::max(x, y) : 0;
+    return largest_size(base, true,
+                        [&](const hgm_opts *o) { return hgm_batch_workspace_size(b, o); });
 }
 
 int hgm_tune(const hgm_csr *g, uint32_t seed, uint32_t *matched_bits, void *workspace,

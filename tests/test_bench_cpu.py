@@ -59,3 +59,19 @@ def test_byte_model_vertex_rounds():
     # the retire writes the dead edges' keys instead of scattering
     assert out["test"] == (12 * 10 + 12 * 30 + 4 * 3 + 9) + (20 * 4 + 12 * 12 + 4 * 4 + 12)
     assert out["retire"] == (8 * 10 + 5 * 30 + 28 * 4 + 8 * 6) + (12 * 4 + 5 * 12 + 8 * 4)
+
+
+def test_byte_model_tail():
+    """Rounds from tail_from on go to the tail: list gathered once (40 B per
+    live edge), then per round test and retire over its compact slots."""
+    three = {"live_edges": [10, 4, 2], "live_pins": [30, 12, 6], "matched_per_round": [3, 1, 2],
+             "matched_pins": [9, 3, 6], "rounds": 3}
+    full = bench.algorithmic_bytes(three, lambda r: False, n=100, pairs=False)
+    out = bench.algorithmic_bytes(three, lambda r: False, n=100, pairs=False, tail_from=1)
+    assert out["scatter"] == full["scatter"]
+    # round 0's test and retire (which builds round 1's list) stay
+    assert out["test"] == 12 * 10 + 20 * 30 + 4 * 3 + 9
+    assert out["retire"] == 8 * 10 + 5 * 30 + 28 * 4 + 8 * 12
+    r1 = (20 * 4 + 12 * 12 + 4 * 1 + 3) + (20 * 4 + 5 * 12 + 20 * 2 + 16 * 6)
+    r2 = (20 * 2 + 12 * 6 + 4 * 2 + 6) + (20 * 2 + 5 * 6)
+    assert out["tail"] == 40 * 4 + r1 + r2

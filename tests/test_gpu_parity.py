@@ -354,35 +354,44 @@ def test_concurrent_calls_on_two_streams(hgm):
     assert not errors, errors
 
 
+@pytest.mark.parametrize("tail", [0, 1 << 30])
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("rps", [0, 1, 3])
-def test_timing_statistics(hgm, variant, rps):
+def test_timing_statistics(hgm, variant, rps, tail):
     """The per-kernel timing that bench.py reports: one test and one retire
     launch per live round (the retire that finds the next live set belongs
     to its round); round 0's maximum once (CRCW: the edge scatter; CREW and
     AUTO here: the vertex pass), and CREW's vertex pass once more in every
     later round; per-round times add up to the kernel times outside setup.
-    Launches past the last live round are not counted."""
+    Launches past the last live round are not counted.  With the tail (here
+    taking over from round 1), the rounds from the one it took over run in
+    one tail launch, whose time belongs to that round."""
     import torch
     g = synth.random_instance(31, 20_000, 50_000, 2, 8, 1, 1000)
     ebits, _, _, ref = _expect(g, 3)
     dg = hgm.DeviceHypergraph.from_host(g, "cuda:0")
-    bits, st = hgm.match(dg, 3, hgm.make_opts(variant, rounds_per_sync=rps), timing=True)
+    bits, st = hgm.match(dg, 3, hgm.make_opts(variant, rounds_per_sync=rps, tail_pins=tail),
+                         timing=True)
     torch.cuda.synchronize()
     assert np.array_equal(bits.cpu().numpy().view(np.uint32), ebits)
     R = st["rounds"]
     assert R == ref["rounds"] and R >= 3
     n = st["kernel_launches"]
-    assert n["test"] == R and n["retire"] == R
+    t0 = R if tail == 0 else n["test"]    # rounds before the tail took over
+    assert n["test"] == t0 and n["retire"] == t0
+    if tail == 0:
+        assert n["tail"] == 0
+    else:
+        assert 1 <= t0 < R and n["tail"] >= 1
     if variant == "crcw":
         assert n["scatter"] == 1 and n["vertex_max"] == 0
-    elif variant == "crew":
-        assert n["scatter"] == 0 and n["vertex_max"] == R
+    elif variant == "crew":   # with the tail, also the pass that forms its first round
+        assert n["scatter"] == 0 and n["vertex_max"] == t0 + (tail != 0)
     else:   # uniform random degrees: AUTO takes the vertex-centric round 0
         assert n["scatter"] == 0 and n["vertex_max"] == 1
     assert n["setup"] >= 1
     ms = st["kernel_ms"]
     assert all(v >= 0 for v in ms.values()) and ms["test"] > 0 and ms["retire"] > 0
-    assert st["round_ms"].size == R and np.all(st["round_ms"] > 0)
+    assert st["round_ms"].size == R and np.all(st["round_ms"][:t0 + (tail != 0)] > 0)
     rounds_total = sum(v for k, v in ms.items() if k != "setup")
     assert abs(float(st["round_ms"].sum()) - rounds_total) <= 1e-3 * rounds_total + 1e-4
