@@ -516,6 +516,114 @@ def ceilings(grid_per_cu=8):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (csv) for profiles/: kernel classes by name.
+
+KERNEL_CLASS = [("k_retire", "retire"), ("k_test", "test"), ("k_max0_edge", "scatter"),
+                ("k_scatter0", "scatter"), ("k_max0_vertex", "vertex_max"),
+                ("k_vertex_max", "vertex_max"), ("k_solo", "solo"), ("k_tail", "tail"),
+                ("k_prologue", "setup"), ("k_init", "setup"), ("k_batch_setup", "setup"),
+                ("k_live0", "setup"), ("k_validate", "setup"), ("k_zero_words", "setup")]
+
+
+def kernel_short_name(name):
+    """'void hgm::(anonymous namespace)::k_test<true, 1, false>(hgm::Graph, ...)'
+    -> 'k_test<true, 1, false>'."""
+    s = name.replace("(anonymous namespace)::", "")
+    s = s.split("(")[0].strip()
+    if s.startswith("void "):
+        s = s[5:]
+    return s.replace("hgm::", "")
+
+
+def kernel_class(name):
+    short = kernel_short_name(name)
+    for key, cls in KERNEL_CLASS:
+        if key in short:
+            return cls
+    return None
+
+
+def _csv_rows(root, suffix):
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if fn.endswith(suffix):
+                with open(os.path.join(dirpath, fn), newline="") as f:
+                    rows += list(csv.DictReader(f))
+    return rows
+
+
+def summarize_trace(root):
+    """Markdown table of a --kernel-trace run: per kernel, dispatches, per
+    call (hgm calls = k_prologue dispatches), total, mean, min and max
+    duration in microseconds."""
+    rows = _csv_rows(root, "kernel_trace.csv")
+    per = {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        cls = kernel_class(name)
+        if cls is None:
+            continue
+        short = kernel_short_name(name)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per.setdefault((short, cls), []).append(d)
+    calls = max(1, sum(len(v) for (k, c), v in per.items() if k.startswith("k_prologue")))
+    out = [f"calls (k_prologue dispatches): {calls}", "",
+           "| kernel | class | dispatches | per call | total us per call | avg us | min us | max us |",
+           "|---|---|---|---|---|---|---|---|"]
+    for (k, c), v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| {k} | {c} | {len(v)} | {len(v) / calls:.1f} | {sum(v) / calls:.1f} | "
+                   f"{sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
+    return "\n".join(out)
+
+
+def _pmc_by_class(root, counter):
+    kib, n = {}, {}
+    for r in _csv_rows(root, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        cls = kernel_class(r["Kernel_Name"])
+        if cls is None:
+            continue
+        kib[cls] = kib.get(cls, 0.0) + float(r["Counter_Value"])
+        n[cls] = n.get(cls, 0) + 1
+    return kib, n
+
+
+def summarize_pmc(workload, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, calls,
+                  copy_mib=1024):
+    """JSON line of calibrated HBM traffic per kernel class and per hgm call:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same
+    counters read for the copy probe's three copies of copy_mib MiB."""
+    # the copy probe's three copies (dispatches whose kernel name says copy;
+    # the fill of its source is left out)
+    def total(root, counter):
+        rows = [r for r in _csv_rows(root, "counter_collection.csv")
+                if r.get("Counter_Name") == counter]
+        copies = [r for r in rows if "copy" in r["Kernel_Name"].lower()]
+        return sum(float(r["Counter_Value"]) for r in (copies or rows))
+    copied_kib = 3 * copy_mib * 1024.0
+    f_meas, w_meas = total(cal_fetch_dir, "FETCH_SIZE"), total(cal_write_dir, "WRITE_SIZE")
+    ff, fw = copied_kib / f_meas, copied_kib / w_meas
+    fk, fn = _pmc_by_class(fetch_dir, "FETCH_SIZE")
+    wk, _ = _pmc_by_class(write_dir, "WRITE_SIZE")
+    kernels = {}
+    for cls in sorted(set(fk) | set(wk)):
+        disp = fn.get(cls, 0)
+        b = (fk.get(cls, 0.0) * ff + wk.get(cls, 0.0) * fw) * 1024.0
+        kernels[cls] = {"dispatches": disp, "fetch_kib": fk.get(cls, 0.0),
+                        "write_kib": wk.get(cls, 0.0), "launches_per_call": disp / calls,
+                        "bytes_per_call": b / calls}
+    return json.dumps({"kernel_source": kernel_source_digest(), "workload": workload,
+                       "calls": calls, "copy_factor": {"fetch": ff, "write": fw,
+                                                       "copy_probe_mib": copy_mib,
+                                                       "fetch_kib_measured": f_meas,
+                                                       "write_kib_measured": w_meas},
+                       "kernels": kernels})
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -637,10 +745,25 @@ def main():
                     help="1: requests also upload the vertex side (default: edge side only)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
+    ap.add_argument("--summarize-trace", default=None,
+                    help="rocprofv3 --kernel-trace output directory (csv): print its table")
+    ap.add_argument("--summarize-pmc", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of the "
+                         "workload and of --copy-probe 1024: print the traffic summary line")
+    ap.add_argument("--calls", type=int, default=0,
+                    help="hgm calls in the profiled run (for --summarize-pmc)")
     ap.add_argument("--ceilings", type=int, default=0,
                     help="1: only measure the memory-system ceilings (streaming, random "
                          "gathers, atomics) and print them as one JSON line")
     args = ap.parse_args()
+
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_pmc:
+        print(summarize_pmc(args.workload, *args.summarize_pmc, calls=max(1, args.calls)))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
