@@ -451,7 +451,9 @@ def ceilings(grid_per_cu=8):
     buffers of 2 MiB (an XCD's L2 holds it), 16 MiB (best[] of the power-law
     workload) and 256 MiB (beyond the Infinity Cache), device-scope 64-bit
     atomic max at random addresses (plain and filtered by a read, as the
-    scatter runs it) over 16 MiB, and on one address."""
+    scatter runs it) over 16 MiB, and on one address; per-launch time of
+    back-to-back empty kernels of the round kernels' shape, on a stream and
+    replayed from a captured HIP graph."""
     import ctypes
     import torch
     from paper_2602_22976_amd import build as hb
@@ -513,6 +515,17 @@ def ceilings(grid_per_cu=8):
                                             grid))
     out["one_address_atomic_max8_G_per_s"] = n1 / (ms * 1e-3) / 1e9
     torch.cuda.synchronize()
+    lib.hgm_probe_launches.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+    cnt = torch.zeros(65536, dtype=torch.int32, device=dev)
+    for g_wg, n_launch in ((2048, 20), (2048, 100), (256, 100)):
+        su, gu = ctypes.c_double(), ctypes.c_double()
+        rc = lib.hgm_probe_launches(cnt.data_ptr(), sink.data_ptr(), g_wg, n_launch, 5,
+                                    ctypes.byref(su), ctypes.byref(gu))
+        if rc == 0:
+            out[f"launch_us_stream_{g_wg}wg_x{n_launch}"] = su.value
+            out[f"launch_us_graph_{g_wg}wg_x{n_launch}"] = gu.value
     return out
 
 

@@ -10,6 +10,8 @@
 //   filtered8   a gather, then the atomic only where the value rises (the
 //               scatter as the kernels run it)
 //   hot8        64-bit atomic max on one address (a hub's best entry)
+//   launches    back-to-back launches of an empty kernel of the round kernels'
+//               shape, on a stream and replayed from a captured HIP graph
 // Indices come from a caller buffer of random uint32 values reduced modulo
 // the element count inside the kernel, read coalesced.  Every kernel folds
 // what it loads into one word per thread so that no load is dead code.
@@ -65,9 +67,67 @@ __global__ void __launch_bounds__(kThreads) k_atomic(uint64_t *p, uint32_t elems
     }
 }
 
+// An almost empty kernel of the round kernels' shape: each workgroup reads
+// one counter and returns (a late round's launch with nothing to do).
+__global__ void __launch_bounds__(kThreads) k_empty(const int *cnt, int *sink) {
+    if (cnt[blockIdx.x] == -1 && threadIdx.x == 0) sink[0] = 1;  // never: cnt holds zeros
+}
+
 }  // namespace
 
 extern "C" {
+
+// Average microseconds per launch of `launches` back-to-back empty kernels
+// of `grid` workgroups: plain stream launches (*stream_us) and the same
+// sequence captured once in a HIP graph and replayed (*graph_us; capture
+// and instantiation are not timed).  cnt: device int[grid] of zeros.
+int hgm_probe_launches(const int *cnt, int *sink, int grid, int launches, int reps,
+                       double *stream_us, double *graph_us) {
+    hipStream_t st;
+    if (hipStreamCreate(&st) != hipSuccess) return -1;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+    auto enqueue = [&]() {
+        for (int i = 0; i < launches; ++i)
+            hipLaunchKernelGGL(k_empty, dim3(grid), dim3(kThreads), 0, st, cnt, sink);
+    };
+    enqueue();  // warm up
+    if (hipStreamSynchronize(st) != hipSuccess) return -1;
+    float ms = 0.f, best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(a, st);
+        enqueue();
+        hipEventRecord(b, st);
+        hipEventSynchronize(b);
+        hipEventElapsedTime(&ms, a, b);
+        best = ms < best ? ms : best;
+    }
+    *stream_us = 1e3 * best / launches;
+    hipGraph_t g;
+    hipGraphExec_t ge;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return -1;
+    enqueue();
+    if (hipStreamEndCapture(st, &g) != hipSuccess) return -1;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) return -1;
+    hipGraphLaunch(ge, st);  // warm up
+    hipStreamSynchronize(st);
+    best = 1e30f;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(a, st);
+        hipGraphLaunch(ge, st);
+        hipEventRecord(b, st);
+        hipEventSynchronize(b);
+        hipEventElapsedTime(&ms, a, b);
+        best = ms < best ? ms : best;
+    }
+    *graph_us = 1e3 * best / launches;
+    hipGraphExecDestroy(ge);
+    hipGraphDestroy(g);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipStreamDestroy(st);
+    return (int)hipGetLastError();
+}
 
 // Each launcher enqueues one probe on `stream` and returns the HIP status.
 int hgm_probe_stream(const void *buf, int64_t bytes, uint32_t *sink, void *stream, int grid) {
