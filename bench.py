@@ -249,7 +249,7 @@ def batched_leg(count, steps):
 
 
 def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
-               edge_side_only=True):
+               edge_side_only=True, solo_max_kappa=0):
     """Open-loop Poisson arrivals at `rate` req/s for `duration` s into the
     request server.  Requests are drawn (seeded) from a pool of pre-generated
     hypergraphs in pinned host memory (kappa log-uniform in [1e3, 1e7],
@@ -267,7 +267,8 @@ def served_leg(rate, duration, pool_count, budget_gb, workers, warmup_s=5.0,
     gen_s = time.perf_counter() - t0
     arrivals = synth.gen.poisson_arrivals(2005, rate, duration)
     pick = np.random.Generator(np.random.PCG64(3005)).integers(0, len(views), size=arrivals.size)
-    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"),
+    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers,
+                     opts=hgm.make_opts("auto", solo_max_kappa=solo_max_kappa),
                      edge_side_only=edge_side_only)
     sched = {}
     done = []
@@ -353,7 +354,8 @@ def served_pool(count, vertex_side=False):
     return views, keep
 
 
-def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s):
+def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s,
+                    solo_max_kappa=0):
     """Saturation throughput of the request server on the served workload's
     pool: a closed loop keeps `inflight` requests submitted (request i draws
     pool entry i mod pool, priority seed i) for `duration` s, counting the
@@ -367,7 +369,8 @@ def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s)
     views, _ = served_pool(pool_count, vertex_side=False)
     order = np.random.Generator(np.random.PCG64(4005)).permutation(len(views))
     req = lambda i: views[order[i % len(views)]]
-    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers, opts=hgm.make_opts("auto"),
+    srv = hgm.Server(int(budget_gb * (1 << 30)), workers=workers,
+                     opts=hgm.make_opts("auto", solo_max_kappa=solo_max_kappa),
                      edge_side_only=True)
     t_start = time.monotonic()
     nxt = 0
@@ -434,6 +437,7 @@ def served_capacity(pool_count, budget_gb, workers, inflight, duration, plain_s)
     cap = len(win) / (t_end - t_win)
     plain = n_plain / t_plain
     return {"pool": len(views), "inflight": inflight, "workers": workers,
+            "solo_max_kappa": solo_max_kappa,
             "duration_s": duration, "completed": len(done),
             "hypergraphs_per_s": cap, "incidences_per_s": kap / (t_end - t_win),
             "p50_ms": float(np.percentile(lat, 50) * 1e3),
@@ -749,11 +753,13 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--capacity-seconds", type=float, default=10.0,
                     help="closed-loop saturation run of the server and plain form (0 = skip)")
-    ap.add_argument("--capacity-inflight", type=int, default=64)
+    ap.add_argument("--capacity-inflight", type=int, default=256)
     ap.add_argument("--tune", type=int, default=1,
                     help="1: default vs autotuned schedules (power-law, hub, batched sample)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-workers", type=int, default=3)
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-solo-max-kappa", type=int, default=0,
+                    help="solo part bound of the server's waves (0 = library default, -1 = off)")
     ap.add_argument("--serve-vertex-side", type=int, default=0,
                     help="1: requests also upload the vertex side (default: edge side only)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -926,12 +932,14 @@ def main():
     if args.serve_seconds > 0:
         result["served"] = served_leg(args.serve_rate, args.serve_seconds, args.serve_pool,
                                       args.serve_budget_gb, args.serve_workers,
-                                      edge_side_only=not args.serve_vertex_side)
+                                      edge_side_only=not args.serve_vertex_side,
+                                      solo_max_kappa=args.serve_solo_max_kappa)
     if args.capacity_seconds > 0:
         result["served_capacity"] = served_capacity(args.serve_pool, args.serve_budget_gb,
                                                     args.serve_workers, args.capacity_inflight,
                                                     args.capacity_seconds,
-                                                    max(2.0, args.capacity_seconds / 2))
+                                                    max(2.0, args.capacity_seconds / 2),
+                                                    args.serve_solo_max_kappa)
     if args.tune:
         del ws
         torch.cuda.empty_cache()

@@ -346,7 +346,10 @@ typedef struct hgm_result {
 typedef struct hgm_server_opts {
     int32_t workers;         /* concurrent waves (threads and streams); 0 = 2 */
     int32_t max_batch;       /* requests per wave at most; 0 = 1024 */
-    hgm_opts match;          /* options of every wave's matching (validate unsupported) */
+    hgm_opts match;          /* options of every wave's matching (validate unsupported;
+                                solo_max_kappa 0 means 2^17 here: a wave holds few
+                                requests, and a large one is faster in the round
+                                kernels than on one compute unit) */
     int32_t edge_side_only;  /* 1: requests carry only the edge side (v_off and v_edges
                                 are ignored and may be NULL); half the bytes to upload,
                                 and every round is edge-centric (with CREW: HGM_E_ARG) */
