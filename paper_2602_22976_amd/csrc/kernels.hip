@@ -107,6 +107,19 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
     return t;
 }
 
+// The work item (edge region or run of vertex chunks) of workgroup b among
+// `grid`.  The dispatcher deals workgroups to the chip's 8 XCDs round-robin
+// (b on XCD b % 8), and each XCD has its own L2: mapping each XCD's
+// workgroups to one contiguous share of the items keeps neighbouring items,
+// e.g. the edges and vertices of one instance of a batch, on one L2 instead
+// of all eight.  A bijection of [0, grid).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int b, int grid) {
+    const int x = b % kXcds, q = b / kXcds;
+    const int per = grid / kXcds, rem = grid % kXcds;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
 // Largest j in [0, kBlock) with start[j] <= t (start non-decreasing, start[0] = 0).
 __device__ __forceinline__ int find_item(const int *start, int t) {
     int j = 0;
@@ -538,7 +551,7 @@ __device__ __forceinline__ void scatter0_region(const Graph &g, const State &s, 
 template <bool kPairs, bool kB>
 __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t kseed) {
     __shared__ ChunkLds L;
-    scatter0_region<kPairs, kB>(g, s, L, blockIdx.x, kseed);
+    scatter0_region<kPairs, kB>(g, s, L, xcd_item(blockIdx.x, gridDim.x), kseed);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,7 +578,7 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
                                                    int rekey) {
     constexpr bool scatter = kScatter;
     __shared__ ChunkLds L;
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     const int cnt = region_count(s, g.m, round - 1, b);
     const int64_t out0 = (int64_t)b * s.region;  // the region's first list slot
     int32_t *out_list = s.list[round & 1] + out0;
@@ -826,7 +839,11 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
         if (lane == 0 && mx) atomic_max_u64(&best[v], mx);
     }
 
-    for (int64_t c0 = (int64_t)blockIdx.x * kBlock; c0 < g.n; c0 += (int64_t)gridDim.x * kBlock) {
+    // The grid sweeps the vertices in steps of gridDim.x chunks (all
+    // workgroups work on neighbouring vertices at a time); within a step each
+    // XCD takes one contiguous share (xcd_item).
+    for (int64_t c0 = (int64_t)xcd_item(blockIdx.x, gridDim.x) * kBlock; c0 < g.n;
+         c0 += (int64_t)gridDim.x * kBlock) {
         const int v = (int)c0 + threadIdx.x;
         int len = 0, base = 0, eb = 0;
         bool own = false;
@@ -926,7 +943,7 @@ __global__ void __launch_bounds__(kBlock) k_max0_edge(Graph g, State s, uint32_t
         return;
     }
     hub_table_build(H, s);
-    scatter0_region<kPairs, kB>(g, s, L, blockIdx.x, seed, &H);
+    scatter0_region<kPairs, kB>(g, s, L, xcd_item(blockIdx.x, gridDim.x), seed, &H);
 }
 
 template <bool kB>
@@ -959,7 +976,7 @@ template <bool kPairs, int kClear, bool kB>
 __global__ void __launch_bounds__(kBlock) k_test(Graph g, State s, int round, uint32_t *bits,
                                                  uint32_t kseed) {
     __shared__ ChunkLds L;
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     const int cnt = region_count(s, g.m, round, b);
     const uint64_t *best = s.best[round & 1];
     uint64_t *next = s.best[(round + 1) & 1];
@@ -1591,7 +1608,7 @@ __device__ __forceinline__ bool live0_keep(const SoloArgs &a, int &i, int64_t e)
 __global__ void __launch_bounds__(kBlock) k_live0_count(Graph g, State s, SoloArgs a) {
     __shared__ int first;
     __shared__ unsigned long long sum_tmp[kWaves];
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     const int64_t lo = (int64_t)b * s.region;
     const int64_t hi = lo + s.region < (int64_t)g.m ? lo + s.region : (int64_t)g.m;
     unsigned long long kept = 0;
@@ -1609,7 +1626,7 @@ __global__ void __launch_bounds__(kBlock) k_live0_place(Graph g, State s, SoloAr
     __shared__ int first;
     __shared__ int wave_tmp[kWaves];
     __shared__ unsigned long long sum_tmp[kWaves];
-    const int b = blockIdx.x;
+    const int b = xcd_item(blockIdx.x, gridDim.x);
     // Kept edges before this workgroup's range, and in all.
     unsigned long long before = 0, all = 0;
     for (int q = threadIdx.x; q < s.grid; q += kBlock) {
