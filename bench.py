@@ -533,6 +533,131 @@ def ceilings(grid_per_cu=8):
     return out
 
 
+def scatter_forms(reps=5):
+    """The per-vertex maximum the round kernels compute (best[v] = max key of
+    v's records), timed in two forms on the same records (median of reps,
+    HIP events on torch's current stream, each form checked equal to the
+    other): filtered device atomics on a cleared best[] (the round kernels'
+    form; the clear timed on its own) and propagation blocking (records
+    binned by vertex range of 2^rb ids, then each range max-reduced in LDS and
+    written whole; phases timed on their own).  Records: (pin, key) of
+    round 0's scatter on the power-law workload (every pin), of its survivors
+    (the pins of a seeded 40% of the edges, in edge order) and of hub-stress
+    survivors (36% of the edges that avoid the hub, which round 0 matches);
+    key = w << 32 | a seeded random 32-bit priority."""
+    import ctypes
+    import numpy as np
+    import torch
+    import synth
+    from paper_2602_22976_amd import build as hb
+    if not os.path.exists(hb.PROBE_LIB):
+        hb.build(force=True)
+    lib = ctypes.CDLL(hb.PROBE_LIB)
+    P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.hgm_probe_scatter_atomic.argtypes = [P, P, I64, P, I64, I, P, I]
+    lib.hgm_probe_scatter_binned.argtypes = [P, P, I64, P, I64, I, P, P, P, P, I, P, I]
+    dev = "cuda:0"
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    stream = torch.cuda.current_stream().cuda_stream
+    rng = np.random.default_rng(11)
+
+    def records(g, keep):
+        sizes = np.diff(g.e_off.astype(np.int64))
+        edge = np.repeat(np.arange(g.m, dtype=np.int64), sizes)
+        sel = keep[edge]
+        pri = rng.integers(0, 2 ** 32, size=g.m, dtype=np.uint64)
+        key = (g.w.astype(np.uint64) << np.uint64(32)) | pri
+        return g.e_pins[sel].astype(np.uint32), key[edge[sel]]
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def median(x):
+        return sorted(x)[len(x) // 2]
+
+    shapes = []
+    g = synth.config_power_law()
+    shapes.append(("power-law round-0 scatter", g.n, *records(g, np.ones(g.m, bool))))
+    shapes.append(("power-law survivors (40% of edges)", g.n,
+                   *records(g, rng.random(g.m) < 0.4)))
+    del g
+    g = synth.config_hub_stress()
+    deg = np.bincount(g.e_pins, minlength=g.n)
+    hub = int(deg.argmax())
+    sizes = np.diff(g.e_off.astype(np.int64))
+    has_hub = np.zeros(g.m, bool)
+    has_hub[np.repeat(np.arange(g.m), sizes)[g.e_pins == hub]] = True
+    shapes.append(("hub-stress survivors (36% of hub-free edges)", g.n,
+                   *records(g, (rng.random(g.m) < 0.36) & ~has_hub)))
+    del g, deg, has_hub, sizes
+    out = []
+    for name, n, vid_h, key_h in shapes:
+        count = len(vid_h)
+        vid = torch.from_numpy(vid_h.view(np.int32)).to(dev)
+        key = torch.from_numpy(key_h.view(np.int64)).to(dev)
+        best_a = torch.empty(n, dtype=torch.int64, device=dev)
+        best_b = torch.empty(n, dtype=torch.int64, device=dev)
+        row = {"records": name, "n": n, "count": count}
+        grid = cus * 8
+        clear_t, scat_t = [], []
+        for _ in range(reps + 1):
+            e0, e1, e2 = ev(), ev(), ev()
+            e0.record()
+            lib.hgm_probe_scatter_atomic(0, 0, 0, best_a.data_ptr(), n, 1, stream, grid)
+            e1.record()
+            lib.hgm_probe_scatter_atomic(vid.data_ptr(), key.data_ptr(), count,
+                                         best_a.data_ptr(), n, 0, stream, grid)
+            e2.record()
+            e2.synchronize()
+            clear_t.append(e0.elapsed_time(e1))
+            scat_t.append(e1.elapsed_time(e2))
+        row["atomic_clear_ms"] = median(clear_t[1:])
+        row["atomic_scatter_ms"] = median(scat_t[1:])
+        for rb in (12, 13, 14):
+            nb = (n + (1 << rb) - 1) >> rb
+            per_bin = torch.bincount((vid.to(torch.int64) & 0xFFFFFFFF) >> rb, minlength=nb)
+            base = torch.zeros(nb + 1, dtype=torch.int64, device=dev)
+            base[1:] = torch.cumsum(per_bin, 0)
+            cursor = torch.zeros(nb, dtype=torch.int32, device=dev)
+            bin_v = torch.empty(count, dtype=torch.int16, device=dev)
+            bin_key = torch.empty(count, dtype=torch.int64, device=dev)
+            for producers in (cus, 2 * cus):
+                w_t, r_t = [], []
+                ok = True
+                for _ in range(reps + 1):
+                    e0, e1, e2 = ev(), ev(), ev()
+                    e0.record()
+                    rc1 = lib.hgm_probe_scatter_binned(
+                        vid.data_ptr(), key.data_ptr(), count, best_b.data_ptr(), n, rb,
+                        base.data_ptr(), cursor.data_ptr(), bin_v.data_ptr(), bin_key.data_ptr(),
+                        1, stream, producers)
+                    e1.record()
+                    rc2 = lib.hgm_probe_scatter_binned(
+                        vid.data_ptr(), key.data_ptr(), count, best_b.data_ptr(), n, rb,
+                        base.data_ptr(), cursor.data_ptr(), bin_v.data_ptr(), bin_key.data_ptr(),
+                        2, stream, producers)
+                    e2.record()
+                    e2.synchronize()
+                    if rc1 or rc2:
+                        ok = False
+                        break
+                    w_t.append(e0.elapsed_time(e1))
+                    r_t.append(e1.elapsed_time(e2))
+                tag = f"binned_rb{rb}_p{producers}"
+                if not ok:
+                    row[tag] = "rejected"
+                    continue
+                row[tag + "_write_ms"] = median(w_t[1:])
+                row[tag + "_reduce_ms"] = median(r_t[1:])
+                row[tag + "_equal"] = bool(torch.equal(best_a, best_b))
+            del bin_v, bin_key
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        del vid, key, best_a, best_b
+        torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Summaries of rocprofv3 output (csv) for profiles/: kernel classes by name.
 
@@ -774,7 +899,8 @@ def main():
                     help="hgm calls in the profiled run (for --summarize-pmc)")
     ap.add_argument("--ceilings", type=int, default=0,
                     help="1: only measure the memory-system ceilings (streaming, random "
-                         "gathers, atomics) and print them as one JSON line")
+                         "gathers, atomics) and print them as one JSON line; 2: only time "
+                         "the per-vertex max by atomics against propagation blocking")
     args = ap.parse_args()
 
     if args.summarize_trace:
@@ -798,6 +924,9 @@ def main():
         sys.exit(1)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.ceilings == 2:
+        print(json.dumps({"scatter_forms": scatter_forms()}), flush=True)
         return
     if args.ceilings:
         print(json.dumps({"ceilings": ceilings()}), flush=True)
