@@ -661,7 +661,7 @@ def scatter_forms(reps=5):
 # ---------------------------------------------------------------------------
 # Summaries of rocprofv3 output (csv) for profiles/: kernel classes by name.
 
-KERNEL_CLASS = [("k_retire", "retire"), ("k_test", "test"), ("k_max0_edge", "scatter"),
+KERNEL_CLASS = [("k_retire", "retire"), ("k_bin_max", "retire"), ("k_test", "test"), ("k_max0_edge", "scatter"),
                 ("k_scatter0", "scatter"), ("k_max0_vertex", "vertex_max"),
                 ("k_vertex_max", "vertex_max"), ("k_solo", "solo"), ("k_tail", "tail"),
                 ("k_prologue", "setup"), ("k_init", "setup"), ("k_batch_setup", "setup"),

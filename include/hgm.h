@@ -44,7 +44,8 @@ extern "C" {
 
 #define HGM_OK 0
 #define HGM_E_ARG (-1)         /* NULL pointer with a non-zero size, negative size, bad option */
-#define HGM_E_CSR (-2)         /* malformed input detected by opts->validate */
+#define HGM_E_CSR (-2)         /* malformed input detected by opts->validate (or by
+                                  the binned maximum, see bin_shift) */
 #define HGM_E_SIZE (-3)        /* kappa >= 2^31, or workspace too small */
 #define HGM_E_ROUND_LIMIT (-4) /* opts->max_rounds rounds ran and live edges remain */
 #define HGM_E_HIP (-5)         /* a HIP runtime call failed */
@@ -140,6 +141,21 @@ typedef struct hgm_opts {
                                 live pins (and at most 65536 live edges), one
                                 workgroup runs every remaining round
                                 (0 = library default: never; -1 = never) */
+    int32_t bin_shift;       /* hgm_match, AUTO with the vertex side, offset
+                                layout: 10..14 = the next round's per-vertex
+                                maximum by propagation blocking instead of
+                                atomics, in rounds with at least n / 2
+                                surviving pins: the retire pass writes each
+                                surviving pin's (vertex, key) record to the
+                                bin of its 2^bin_shift-vertex range (hub pins
+                                excepted) and one workgroup per bin reduces
+                                it in LDS.  At most 1024 bins, else off.
+                                Needs 10 kappa bytes more workspace.  Pays
+                                where most pins lie on low-degree vertices.
+                                0 = library default (off); -1 = off.  The
+                                bins' capacities are v_off's degree sums, so
+                                a v_off that is not e_pins' transpose can
+                                overflow one: HGM_E_CSR. */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */

@@ -52,10 +52,11 @@ class HgmOpts(ctypes.Structure):
                 ("pairs", ctypes.c_int32), ("solo_max_kappa", ctypes.c_int32),
                 ("edge_grid", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("clear_ratio", ctypes.c_int32), ("hot_degree", ctypes.c_int32),
-                ("first_batch_pct", ctypes.c_int32), ("tail_pins", ctypes.c_int32)]
+                ("first_batch_pct", ctypes.c_int32), ("tail_pins", ctypes.c_int32),
+                ("bin_shift", ctypes.c_int32)]
 
 SCHEDULE_FIELDS = ["hub_threshold", "solo_max_kappa", "edge_grid", "blocks_per_cu",
-                   "clear_ratio", "hot_degree", "first_batch_pct", "tail_pins"]
+                   "clear_ratio", "hot_degree", "first_batch_pct", "tail_pins", "bin_shift"]
 
 
 class HgmBatch(ctypes.Structure):
@@ -331,7 +332,7 @@ class DeviceBatch:
 def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False,
               max_rounds=0, reseed=False, pairs=False, solo_max_kappa=0, edge_grid=0,
               blocks_per_cu=0, clear_ratio=0, hot_degree=0, first_batch_pct=0,
-              tail_pins=0) -> HgmOpts:
+              tail_pins=0, bin_shift=0) -> HgmOpts:
     o = HgmOpts()
     o.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     o.hub_threshold = hub_threshold
@@ -344,6 +345,7 @@ def make_opts(variant="auto", hub_threshold=0, rounds_per_sync=0, validate=False
     o.edge_grid, o.blocks_per_cu, o.clear_ratio = edge_grid, blocks_per_cu, clear_ratio
     o.hot_degree, o.first_batch_pct = hot_degree, first_batch_pct
     o.tail_pins = tail_pins
+    o.bin_shift = bin_shift
     return o
 
 

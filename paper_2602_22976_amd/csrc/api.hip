@@ -48,6 +48,12 @@ constexpr int kDefaultTailPins = -1;
 constexpr int kTailCap = 1 << 16;
 // Rows of the tail record copied with the round counters at each check.
 constexpr int kTailRowsFirst = 64;
+// Binned maximum (bin_shift > 0): a round uses it when the host expects at
+// least n / 2 surviving pins (below that the reduction's fixed cost, one
+// launch and a pass over every bin, outweighs the atomics it saves).  Off by
+// default: it won on hub-stress (uniform degrees, 1.29 -> 1.24 ms) and lost
+// on power-law (skewed degrees, whose filtered atomics are cheap: 1.05 ->
+// 1.11 ms); the autotuner tries it per shape.
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -56,8 +62,8 @@ struct Layout {
     size_t key, eseed, best0, best1, done, list0, list1, cnt0, cnt1, rec[2][5], stats, err, live_key, vedges0,
         vedges1, vlen0, vlen1, pieces,
         piece_count, hot, wrange, vbits, goff, vbase, bitoff, gvoff, ebase, solo, tail_list[2][4],
-        tail, total;
-    int ring, grid, region, piece_cap, solo_rounds, tail_cap;
+        tail, bin_v, bin_key, bin_cursor, total;
+    int ring, grid, region, piece_cap, solo_rounds, tail_cap, bin_rb, bin_nb;
 };
 
 // Edge schedule: `grid` workgroups, each owning `region` consecutive edge ids
@@ -74,6 +80,7 @@ struct Opts {
     int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part)
     int edge_grid, blocks_per_cu, clear_ratio, hot_degree, first_batch_pct;  // 0 = per kind
     int64_t tail_pins;  // one instance: tail bound (-1: no tail)
+    int bin_shift;      // binned maximum: log2 vertices per bin, <= 0 off
     bool reseed;            // priorities redrawn every round (round_seed)
     bool pairs;             // graph: two pins per edge at e_pins[2e], no offsets
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
@@ -113,6 +120,10 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     o->first_batch_pct = d.first_batch_pct;  // 0: resolved per instance (graphs differ)
     if (d.tail_pins < -1) return HGM_E_ARG;
     o->tail_pins = d.tail_pins == 0 ? kDefaultTailPins : d.tail_pins;
+    if (d.bin_shift != -1 && d.bin_shift != 0 &&
+        (d.bin_shift < kBinMinShift || d.bin_shift > kBinMaxShift))
+        return HGM_E_ARG;
+    o->bin_shift = d.bin_shift;
     return HGM_OK;
 }
 
@@ -128,6 +139,19 @@ bool crew_round(const Opts &o, int r) {
 
 bool any_crew_round(const Opts &o) { return crew_round(o, 0); }
 bool uses_live_key(const Opts &o) { return o.variant == HGM_VARIANT_CREW; }
+
+// log2 of the vertices per bin of the binned maximum, or 0 without bins.  It
+// needs the vertex side (the bins' capacities are degree sums, v_off), hub
+// pieces (hub pins stay out of the bins) and the CRCW rounds' offset layout
+// of one instance: AUTO with the vertex side.
+int bin_shift_for(int64_t n, int64_t kappa, const Opts &o, bool batch) {
+    if (batch || o.pairs || o.variant != HGM_VARIANT_AUTO || !o.have_vertex_side ||
+        o.bin_shift <= 0 || n <= 0 || kappa <= 0)
+        return 0;
+    const int rb = o.bin_shift;
+    const int64_t nb = (n + ((int64_t)1 << rb) - 1) >> rb;
+    return nb <= kBinMaxBins ? rb : 0;
+}
 
 Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batch = false) {
     Layout L;
@@ -196,6 +220,13 @@ Layout make_layout(int64_t n, int64_t m, int64_t kappa, const Opts &o, bool batc
         for (int f = 0; f < 4; ++f)
             L.tail_list[k][f] = take((f == 3 ? 8 : 4) * (size_t)L.tail_cap);
     L.tail = take(L.tail_cap ? 8 * ((size_t)kTailHeader + 5 * ((size_t)L.tail_cap + 2)) : 0);
+    // Binned maximum: records (index in bin, key) at the bins' degree-sum
+    // offsets, and a cursor per bin.
+    L.bin_rb = bin_shift_for(n, kappa, o, batch);
+    L.bin_nb = L.bin_rb ? (int)((n + ((int64_t)1 << L.bin_rb) - 1) >> L.bin_rb) : 0;
+    L.bin_v = take(L.bin_nb ? 2 * (size_t)kappa : 0);
+    L.bin_key = take(L.bin_nb ? 8 * (size_t)kappa : 0);
+    L.bin_cursor = take(L.bin_nb ? 4 * (size_t)kBinMaxBins : 0);  // same size for every shift
     L.total = at;
     return L;
 }
@@ -250,6 +281,11 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.tail = L.tail_cap ? (unsigned long long *)(b + L.tail) : nullptr;
     s.tail_cap = L.tail_cap;
     s.tail_pins = o.tail_pins;
+    s.bin_v = L.bin_nb ? (uint16_t *)(b + L.bin_v) : nullptr;
+    s.bin_key = L.bin_nb ? (uint64_t *)(b + L.bin_key) : nullptr;
+    s.bin_cursor = L.bin_nb ? (uint32_t *)(b + L.bin_cursor) : nullptr;
+    s.bin_rb = L.bin_rb;
+    s.bin_nb = L.bin_nb;
     return s;
 }
 
@@ -596,7 +632,12 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                                                                                     : kClearPins;
             HGM_TRY(launch_test(L, g, s, r, clear, matched_bits, kseed(r)));
             HGM_TRY(T.after(HGM_K_TEST, r));
-            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1), o.reseed ? 1 : 0));
+            // The next maximum by bins when the host expects at least n / 2
+            // surviving pins (correct either way).
+            const bool binned =
+                s.bin_nb > 0 && !next_crew && 2.0 * predicted_pins(r + 1) >= (double)g.n;
+            HGM_TRY(launch_retire(L, g, s, r + 1, next_crew ? 0 : 1, kseed(r + 1), o.reseed ? 1 : 0,
+                                  binned ? 1 : 0));
             HGM_TRY(T.after(HGM_K_RETIRE, r));
             if (next_crew) {
                 HGM_TRY(launch_vertex_max(L, g, s, r + 1, kseed(r + 1), o.reseed ? 1 : 0));
@@ -628,6 +669,9 @@ int run_rounds(const Graph &g, const Opts &o, const Layout &lay, const State &s,
                                    sizeof(unsigned long long) * tail_head.size(),
                                    hipMemcpyDeviceToHost, L.stream));
         HGM_TRY(hipStreamSynchronize(L.stream));
+        // A bin that overflowed means v_off does not describe e_pins' transpose.
+        for (int r = first; r <= launched; ++r)
+            if (ring[r % lay.ring].bin_overflow) return HGM_E_CSR;
         auto sum = [](const unsigned long long *a) {
             unsigned long long t = 0;
             for (int i = 0; i < kSub; ++i) t += a[i];

@@ -51,6 +51,9 @@ struct RoundStats {
     unsigned long long weight[kSub];   // their total weight
     unsigned long long mpins[kSub];    // their total size
     unsigned long long form;           // round 0 only: 1 edge-centric, 2 vertex-centric maximum
+    unsigned long long bin_overflow;   // binned maximum: a bin received more records than
+                                       // its vertices' degrees allow (v_off is not the
+                                       // transpose of e_pins); those records were dropped
 };
 
 // The hypergraph as the kernels see it.  A batch of independent instances is
@@ -153,7 +156,21 @@ struct State {
     unsigned long long *tail;
     int32_t tail_cap;          // live edges the tail takes at most
     int64_t tail_pins;         // it takes over a round with at most this many live pins
+    // Binned maximum (one instance, offset layout, vertex side given): the
+    // retire pass writes each surviving non-hub pin's record (pin's index in
+    // its bin, key) to the bin of 2^bin_rb consecutive vertices holding it,
+    // and k_bin_max reduces every bin in LDS.  Bin j's records sit at
+    // v_off[j << bin_rb] + [0, bin_cursor[j]): the bin's vertices' degrees
+    // bound its records in any round.  bin_nb = 0: no bins.
+    uint16_t *bin_v;           // [kappa]
+    uint64_t *bin_key;         // [kappa]
+    uint32_t *bin_cursor;      // [bin_nb] records written, zero between passes
+    int32_t bin_rb, bin_nb;
 };
+
+constexpr int kBinMaxBins = 1024;     // bins of one instance at most
+constexpr int kBinMinShift = 10, kBinMaxShift = 14;  // 2^14 keys = 128 KB of LDS
+constexpr int kBinThreads = 1024;     // workgroup of k_bin_max
 
 // Tail record: word 0 = 1 + the round the tail took over at (0: not taken),
 // word 1 = the rounds of the whole matching when it finished, word 2 =
@@ -220,8 +237,10 @@ hipError_t launch_solo(const Launch &L, const Graph &g, const State &s, const So
 hipError_t launch_live0(const Launch &L, const Graph &g, const State &s, const SoloArgs &a);
 hipError_t launch_validate(const Launch &L, const Graph &g, const State &s, int check_dual);
 hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint32_t kseed);
+// binned (CRCW form, one instance, offset layout, s.bin_nb > 0): the next
+// round's maximum by bins (k_retire_bin, then k_bin_max) instead of atomics.
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
-                         uint32_t kseed, int rekey);
+                         uint32_t kseed, int rekey, int binned = 0);
 hipError_t launch_vertex_max(const Launch &L, const Graph &g, const State &s, int round,
                              uint32_t kseed, int rekey);
 // Round-0 maximum in the form chosen from the degree profile (AUTO): two

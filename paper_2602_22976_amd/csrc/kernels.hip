@@ -293,6 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_prologue(Graph g, State s) {
     }
     if (s.solo && threadIdx.x < kSoloHeader) s.solo[threadIdx.x] = 0;
     if (s.tail && threadIdx.x < kTailHeader) s.tail[threadIdx.x] = 0;
+    for (int j = threadIdx.x; j < s.bin_nb; j += blockDim.x) s.bin_cursor[j] = 0;
     if (threadIdx.x < kSub) {
         s.hot[threadIdx.x] = 0;
         s.wrange[2 * threadIdx.x] = 0xFFFFFFFFu;
@@ -573,11 +574,59 @@ __global__ void __launch_bounds__(kBlock) k_scatter0(Graph g, State s, uint32_t 
 // kPairs: graph layout; kScatter: the CRCW form (else CREW).  Each
 // combination is its own kernel: a kernel holding every path runs the hot
 // one slower.
-template <bool kPairs, bool kScatter, bool kB>
-__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed,
-                                                   int rekey) {
+// Binned form of the scatter (kBin, CRCW, one instance, offset layout): the
+// first pass counts the survivors' non-hub pins per bin in LDS (bcnt) while
+// hub pins are reduced in the hub table H, as in round 0's edge scatter.
+// After the last chunk the workgroup reserves its run in every bin with one
+// device atomic on the bin's cursor, pushes the hub maxima, and a second
+// pass over its just-compacted survivors writes each non-hub pin's record
+// into its run.  k_bin_max then reduces each bin.
+constexpr uint32_t kBinOverflow = 0x80000000u;  // run position of a bin that overflowed
+
+__device__ __forceinline__ void bin_count_chunk(const ChunkLds &L, const int32_t *e_pins,
+                                                int total, HubTable &H, uint32_t *bcnt, int rb) {
+    for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
+        int jj[kUnroll], pin[kUnroll];
+        chunk_pins<false>(L, e_pins, total, t0, jj, pin);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (jj[u] < 0) continue;
+            const int h = hub_find(H, pin[u]);
+            if (h >= 0) {
+                const unsigned long long k = L.key[jj[u]];
+                if (H.mx[h] < k) atomicMax(&H.mx[h], k);
+            } else {
+                atomicAdd(&bcnt[pin[u] >> rb], 1u);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void bin_write_chunk(const ChunkLds &L, const int32_t *e_pins,
+                                                int total, const HubTable &H, uint32_t *bpos,
+                                                int rb, uint16_t *bin_v, uint64_t *bin_key) {
+    const int mask = (1 << rb) - 1;
+    for (int t0 = threadIdx.x; t0 < total; t0 += kUnroll * kBlock) {
+        int jj[kUnroll], pin[kUnroll];
+        chunk_pins<false>(L, e_pins, total, t0, jj, pin);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (jj[u] < 0 || hub_find(H, pin[u]) >= 0) continue;
+            const uint32_t at = atomicAdd(&bpos[pin[u] >> rb], 1u);
+            if (at < kBinOverflow) {
+                bin_v[at] = (uint16_t)(pin[u] & mask);
+                bin_key[at] = L.key[jj[u]];
+            }
+        }
+    }
+}
+
+template <bool kPairs, bool kScatter, bool kB, bool kBin>
+__device__ __forceinline__ void retire_body(const Graph &g, const State &s, int round,
+                                            uint32_t kseed, int rekey, ChunkLds &L, HubTable *H,
+                                            uint32_t *bcnt) {
+    static_assert(!kBin || (kScatter && !kPairs && !kB), "bins: CRCW, one instance, offsets");
     constexpr bool scatter = kScatter;
-    __shared__ ChunkLds L;
     const int b = xcd_item(blockIdx.x, gridDim.x);
     const int cnt = region_count(s, g.m, round - 1, b);
     const int64_t out0 = (int64_t)b * s.region;  // the region's first list slot
@@ -595,6 +644,11 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
                 if (s.vlen[0]) s.vlen[round & 1][pc.x] = 0;
             }
         }
+    }
+    if constexpr (kBin) {
+        hub_table_build(*H, s);
+        for (int j = threadIdx.x; j < s.bin_nb; j += kBlock) bcnt[j] = 0;
+        __syncthreads();
     }
     int out_pos = 0;                 // survivors written so far (uniform)
     unsigned long long kap_acc = 0;  // their pins (thread 0's copy is the total)
@@ -702,9 +756,61 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
         if (scatter) {
             L.start[threadIdx.x] = st2;
             __syncthreads();
-            scatter_chunk<kB>(L, g.e_pins, total2, best);
+            if constexpr (kBin)
+                bin_count_chunk(L, g.e_pins, total2, *H, bcnt, s.bin_rb);
+            else
+                scatter_chunk<kB>(L, g.e_pins, total2, best);
         }
         __syncthreads();
+    }
+    if constexpr (kBin) {
+        // Runs: bin j's records of this workgroup go to bpos[j] onwards.
+        uint32_t *bpos = bcnt + s.bin_nb;
+        const int rb = s.bin_rb;
+        for (int j = threadIdx.x; j < s.bin_nb; j += kBlock) {
+            const uint32_t c = bcnt[j];
+            uint32_t p = 0;
+            if (c) {
+                const int64_t v0 = (int64_t)j << rb;
+                const int lo = g.v_off[v0];
+                const int hi = g.v_off[min(v0 + ((int64_t)1 << rb), (int64_t)g.n)];
+                const uint32_t got = atomicAdd(&s.bin_cursor[j], c);
+                if (lo < 0 || hi > g.kappa || (int64_t)lo + got + c > (int64_t)hi) {
+                    p = kBinOverflow;
+                    atomicAdd(&st_out->bin_overflow, 1ull);
+                } else {
+                    p = (uint32_t)lo + got;
+                }
+            }
+            bpos[j] = p;
+        }
+        for (int i = threadIdx.x; i < kHubSlots; i += kBlock) {
+            const int v = H->id[i];
+            const uint64_t k = H->mx[i];
+            if (v >= 0 && k && load_lower_bound(&best[v]) < k) atomic_max_u64(&best[v], k);
+        }
+        __syncthreads();
+        // Second pass over the survivors this workgroup compacted above (its
+        // own writes, visible after the barrier).
+        for (int c0 = 0; c0 < out_pos; c0 += kBlock) {
+            const int i = c0 + threadIdx.x;
+            int len = 0, base = 0;
+            uint64_t key = 0;
+            if (i < out_pos) {
+                const int64_t at = out0 + i;
+                base = s.rec_a[ko][at];
+                len = s.rec_b[ko][at];
+                key = s.rec_key[ko][at];
+            }
+            int total;
+            const int st = block_exclusive_sum(len, L.wave_tmp, &total);
+            L.start[threadIdx.x] = st;
+            L.base[threadIdx.x] = base;
+            L.key[threadIdx.x] = key;
+            __syncthreads();
+            bin_write_chunk(L, g.e_pins, total, *H, bpos, rb, s.bin_v, s.bin_key);
+            __syncthreads();
+        }
     }
     if (threadIdx.x == 0) {
         s.cnt[round & 1][b] = out_pos;
@@ -713,6 +819,68 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
             atomicAdd(&st_out->kappa[b % kSub], kap_acc);
         }
     }
+}
+
+template <bool kPairs, bool kScatter, bool kB>
+__global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, uint32_t kseed,
+                                                   int rekey) {
+    __shared__ ChunkLds L;
+    retire_body<kPairs, kScatter, kB, false>(g, s, round, kseed, rekey, L, nullptr, nullptr);
+}
+
+// The binned form; dynamic LDS: bin counts, then run positions (2 bin_nb words).
+__global__ void __launch_bounds__(kBlock) k_retire_bin(Graph g, State s, int round,
+                                                       uint32_t kseed, int rekey) {
+    __shared__ ChunkLds L;
+    __shared__ HubTable H;
+    extern __shared__ uint32_t bcnt[];
+    retire_body<false, true, false, true>(g, s, round, kseed, rekey, L, &H, bcnt);
+}
+
+// Reduces bin j (workgroup j): the maximum key of each of its vertices over
+// the records the retire pass wrote, in an LDS tile of 2^bin_rb keys, then
+// raised into best[round & 1] where nonzero (the test cleared the others, as
+// for the atomic form; hub vertices got theirs from the retire pass).  Resets
+// the bin's cursor for the next round.
+__global__ void __launch_bounds__(kBinThreads) k_bin_max(Graph g, State s, int round) {
+    extern __shared__ unsigned long long tile[];
+    const int j = blockIdx.x;
+    const int rb = s.bin_rb;
+    const int64_t v0 = (int64_t)j << rb;
+    const int64_t v1 = min(v0 + ((int64_t)1 << rb), (int64_t)g.n);
+    const int lo = max(g.v_off[v0], 0);
+    const int hi = (int)min((int64_t)g.v_off[v1], g.kappa);
+    const int64_t c = min((int64_t)s.bin_cursor[j], (int64_t)hi - lo);  // < 0: nothing
+    const int nv = (int)(v1 - v0);
+    for (int t = threadIdx.x; t < nv; t += kBinThreads) tile[t] = 0;
+    __syncthreads();
+    const uint16_t *bv = s.bin_v + lo;
+    const uint64_t *bk = s.bin_key + lo;
+    constexpr int64_t step = (int64_t)kUnroll * kBinThreads;
+    for (int64_t i0 = threadIdx.x; i0 < c; i0 += step) {
+        uint16_t v[kUnroll];
+        uint64_t k[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBinThreads;
+            v[u] = i < c ? bv[i] : 0;
+            k[u] = i < c ? bk[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (k[u] && v[u] < nv) atomicMax(&tile[v[u]], (unsigned long long)k[u]);
+    }
+    __syncthreads();
+    // Only this workgroup writes the bin's entries during the kernel; an entry
+    // may already hold a hub maximum pushed by the retire pass (a workgroup
+    // whose table holds a hub that another workgroup's full table left out
+    // sends it to the bins instead), so the larger of the two stays.
+    uint64_t *best = s.best[round & 1];
+    for (int t = threadIdx.x; t < nv; t += kBinThreads) {
+        const uint64_t x = tile[t];
+        if (x && x > best[v0 + t]) best[v0 + t] = x;
+    }
+    if (threadIdx.x == 0) s.bin_cursor[j] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1985,8 +2153,27 @@ hipError_t launch_scatter(const Launch &L, const Graph &g, const State &s, uint3
 }
 
 hipError_t launch_retire(const Launch &L, const Graph &g, const State &s, int round, int scatter,
-                         uint32_t kseed, int rekey) {
+                         uint32_t kseed, int rekey, int binned) {
     const dim3 grid(s.grid), block(kBlock);
+    if (binned) {
+        if (!scatter || g.pairs || g.vbase || s.bin_nb <= 0 || s.bin_nb > kBinMaxBins ||
+            s.bin_rb < kBinMinShift || s.bin_rb > kBinMaxShift || !g.v_off)
+            return hipErrorInvalidValue;
+        const size_t tile = (size_t)8 << s.bin_rb;
+        static std::atomic<size_t> granted{0};
+        if (granted.load(std::memory_order_relaxed) < tile) {
+            hipError_t rc = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_bin_max),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                (int)tile);
+            if (rc != hipSuccess) return rc;
+            granted.store(tile, std::memory_order_relaxed);
+        }
+        hipLaunchKernelGGL(k_retire_bin, grid, block, 8 * (size_t)s.bin_nb, L.stream, g, s, round,
+                           kseed, rekey);
+        hipLaunchKernelGGL(k_bin_max, dim3(s.bin_nb), dim3(kBinThreads), tile, L.stream, g, s,
+                           round);
+        return hipGetLastError();
+    }
 #define HGM_RETIRE(P, S, B) \
     hipLaunchKernelGGL((k_retire<P, S, B>), grid, block, 0, L.stream, g, s, round, kseed, rekey)
     if (g.pairs) {

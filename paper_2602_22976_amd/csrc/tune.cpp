@@ -56,6 +56,7 @@ std::vector<Knob> knobs(bool batch) {
         {"clear", &hgm_opts::clear_ratio, {2, 8, 32}, 0},
         {"first", &hgm_opts::first_batch_pct, {25, 40, 55}, 0},
         {"tail", &hgm_opts::tail_pins, {-1, 1024, 4096, 32768}, 2},
+        {"bins", &hgm_opts::bin_shift, {0, 12, 13, 14}, 2},
     };
     std::vector<Knob> out;
     for (auto &x : k)
@@ -64,7 +65,8 @@ std::vector<Knob> knobs(bool batch) {
 }
 
 // Fields at the candidates that need the most workspace: the lowest hub
-// threshold (the hub pieces), a solo part and a tail; every edge grid is
+// threshold (the hub pieces), a solo part, a tail and bins (their size does
+// not depend on the shift; the widest bins fit the most instances); every edge grid is
 // sized separately (largest_size).
 constexpr int32_t kMinTunedHub = 1024;
 
@@ -75,6 +77,7 @@ hgm_opts largest_workspace(const hgm_opts *base) {
     o.hub_threshold = o.hub_threshold ? std::min(o.hub_threshold, kMinTunedHub) : kMinTunedHub;
     if (o.solo_max_kappa < 0) o.solo_max_kappa = 0;
     if (o.tail_pins <= 0) o.tail_pins = 32768;
+    if (o.bin_shift >= 0) o.bin_shift = 14;  // bins wherever any candidate shift allows them
     return o;
 }
 

@@ -54,19 +54,21 @@ def _csr(n, m, kappa):
 
 def test_workspace_size_layout(lib):
     small = hgm.hgm_workspace_size(_csr(10, 20, 100))
-    big = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000))
+    nobins = hgm.make_opts(bin_shift=-1)
+    big = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), nobins)
     assert 0 < small < big
     # two max buffers 16n, done n, two lists with their edge records (id 4,
     # pin offset 4, pin count 4, first pin 4, key 8) 48m at least; keys are
     # not stored per edge for one instance
     assert big >= 48 * 5_000_000 + 17 * 2_000_000
     assert big < 48 * 5_000_000 + 17 * 2_000_000 + 8 * 5_000_000
-    rs = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts(reseed=True))
+    rs = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000),
+                                hgm.make_opts(reseed=True, bin_shift=-1))
     assert rs == big
     crew = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000), hgm.make_opts("crew"))
     assert crew > big
     val = hgm.hgm_workspace_size(_csr(2_000_000, 5_000_000, 30_000_000),
-                                 hgm.make_opts(validate=True))
+                                 hgm.make_opts(validate=True, bin_shift=-1))
     assert val >= big + 30_000_000 // 8 - 4096
     assert hgm.hgm_workspace_size(_csr(-1, 5, 5)) == 0
     assert hgm.hgm_workspace_size(_csr(5, 5, 2 ** 31)) == 0
@@ -77,6 +79,34 @@ def test_workspace_size_layout(lib):
     bad = hgm.make_opts()
     bad.reseed = 2
     assert hgm.hgm_workspace_size(_csr(5, 5, 5), bad) == 0
+
+
+def test_workspace_bins(lib):
+    """The binned maximum's records (2-byte index and 8-byte key per pin) and
+    cursors are carved only where bins run: an explicit shift, AUTO with the
+    vertex side, offset layout, at most 1024 bins."""
+    big = _csr(2_000_000, 5_000_000, 30_000_000)
+    off = hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=-1))
+    assert hgm.hgm_workspace_size(big) == off  # off by default
+    on = hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=12))
+    assert 10 * 30_000_000 <= on - off <= 10 * 30_000_000 + 3 * 4096 + 1024
+    for rb in (13, 14):  # same size for every shift that fits
+        assert hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=rb)) == on
+    # 2^21 vertices in bins of 2^10 would be 1954 bins: no bins
+    assert hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=10)) == off
+    # CRCW, CREW, graphs and instances without the vertex side have no bins
+    for variant in ("crcw", "crew"):
+        assert hgm.hgm_workspace_size(big, hgm.make_opts(variant, bin_shift=12)) == \
+            hgm.hgm_workspace_size(big, hgm.make_opts(variant))
+    edge_only = _csr(2_000_000, 5_000_000, 30_000_000)
+    edge_only.v_off = edge_only.v_edges = None
+    assert hgm.hgm_workspace_size(edge_only, hgm.make_opts(bin_shift=12)) == \
+        hgm.hgm_workspace_size(edge_only)
+    small = _csr(1000, 2000, 8000)
+    assert hgm.hgm_workspace_size(small, hgm.make_opts(bin_shift=10)) >= \
+        hgm.hgm_workspace_size(small) + 10 * 8000
+    for bad in (1, 9, 15, -2):
+        assert hgm.hgm_workspace_size(small, hgm.make_opts(bin_shift=bad)) == 0
 
 
 def test_match_rejects_bad_arguments_without_gpu(lib):

@@ -318,6 +318,15 @@ def test_hub_stress_full(hgm, hub_stress, variant):
     _check(hgm, g, 1, variant, expect=ex)
 
 
+@pytest.mark.parametrize("shift", [12, 14])
+def test_full_bins(hgm, power_law, hub_stress, shift):
+    """The binned next-round maximum (bins of 2^shift vertices) on both
+    full-size instances."""
+    for g, ex in (power_law, hub_stress):
+        print(f"full n={g.n} m={g.m} bin_shift={shift}", flush=True)
+        _check(hgm, g, 1, "auto", expect=ex, bin_shift=shift)
+
+
 def test_concurrent_calls_on_two_streams(hgm):
     """Two host threads call hgm_match at once, each on its own stream and
     workspace (with per-kernel timing on, which keeps a per-thread event
