@@ -123,7 +123,8 @@ typedef struct hgm_opts {
      * shape).  0 = library default for each. */
     int32_t edge_grid;       /* workgroups of the edge-centric kernels, each
                                 owning a fixed range of edge ids (default
-                                2048, at most 65536) */
+                                1536 for one instance, 4096 for a batch; at
+                                most 65536) */
     int32_t blocks_per_cu;   /* workgroups per compute unit of the vertex-
                                 centric and setup kernels (default 8, at
                                 most 32) */

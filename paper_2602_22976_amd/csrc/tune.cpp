@@ -49,7 +49,7 @@ struct Knob {
 std::vector<Knob> knobs(bool batch) {
     std::vector<Knob> k = {
         {"solo", &hgm_opts::solo_max_kappa, {-1, 1 << 16, 1 << 18, 1 << 20, 1 << 22}, 1},
-        {"grid", &hgm_opts::edge_grid, {512, 1024, 2048, 4096, 8192, 16384}, 0},
+        {"grid", &hgm_opts::edge_grid, {512, 1024, 1536, 2048, 3072, 4096, 8192, 16384}, 0},
         {"bpc", &hgm_opts::blocks_per_cu, {2, 4, 8, 16}, 0},
         {"hub", &hgm_opts::hub_threshold, {1024, 4096, 8192, 32768, 1 << 30}, 0},
         {"hot", &hgm_opts::hot_degree, {16, 64, 256}, 0},
