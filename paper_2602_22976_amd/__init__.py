@@ -357,6 +357,12 @@ def alloc_batch_workspace(db: DeviceBatch, opts: HgmOpts | None = None):
     return torch.empty(nbytes, dtype=torch.uint8, device=db.e_pins.device)
 
 
+# Per-round rows the wrappers collect unless a call asks for more (`cap`):
+# instances that need more rounds are paths and chains of thousands of edges;
+# "rounds" is exact either way, the per-round arrays then stop at the cap.
+STATS_CAP = 4096
+
+
 def _stats_struct(cap, timing):
     import numpy as np
     arrays = [np.zeros(max(cap, 1), dtype=np.int64) for _ in range(4)]
@@ -395,7 +401,7 @@ def match_batch(db: DeviceBatch, opts: HgmOpts | None = None, workspace=None, bi
         bits = torch.empty(max(db.words_total, 1), dtype=torch.int32, device=dev)
     st = arrays = rms = None
     if want_stats or timing:
-        st, arrays, rms = _stats_struct(min(db.m_total + 1, 1 << 16) if cap is None else cap,
+        st, arrays, rms = _stats_struct(min(db.m_total + 1, STATS_CAP) if cap is None else cap,
                                         timing)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
@@ -427,7 +433,7 @@ def match(dg: DeviceHypergraph, seed: int, opts: HgmOpts | None = None, workspac
         bits = torch.empty(max(words, 1), dtype=torch.int32, device=dev)
     st = arrays = rms = None
     if want_stats or timing:
-        st, arrays, rms = _stats_struct(min(dg.m + 1, 1 << 16) if cap is None else cap, timing)
+        st, arrays, rms = _stats_struct(min(dg.m + 1, STATS_CAP) if cap is None else cap, timing)
     if stream is None:
         stream = torch.cuda.current_stream(dev).cuda_stream
     rc = hgm_match(dg.csr(), seed, bits.data_ptr(), workspace.data_ptr(), workspace.numel(),
