@@ -11,6 +11,7 @@
 
 #include "hgm.h"
 #include "internal.h"
+#include "schedule.h"
 
 using namespace hgm;
 
@@ -19,47 +20,20 @@ namespace {
 constexpr int kFirstBatch = 4;         // fewest rounds enqueued before the first termination check
 constexpr int kAdaptiveMaxBatch = 32;  // cap of a predicted batch
 constexpr int kMaxRoundsPerSync = 200;
-constexpr int kDefaultHubThreshold = 8192;
-// Schedule defaults (hgm_opts fields of the same meaning; hgm_tune searches
-// around them).
-constexpr int kBlocksPerCu = 8;
-// Workgroups of the edge kernels (fixed, device independent, so that the
-// workspace size does not depend on the device).  Swept on the MI355X (256
-// CUs): one instance runs fastest at 1536 (power-law 1.030 -> 0.945 ms
-// against 2048, hub-stress 1.287 -> 1.253, graphs 3-4% faster), a batch's
-// round kernels at 4096 (18.3 -> 16.9 ms on 4,096 instances).
-constexpr int kEdgeGrid = 1536;
-constexpr int kEdgeGridBatch = 4096;
-// The test clears the whole next maximum buffer by streaming when a round has
-// at least n / kFullClearRatio live pins, else at each pin it visits.
-constexpr int kFullClearRatio = 8;
-constexpr int kHotDegree = 64;        // AUTO's round-0 form: degree of a hot vertex
-constexpr int kFirstBatchPct = 40;    // first batch of rounds: 0.40 log2(kappa)
-constexpr int kFirstBatchPctGraph = 35;
 // Per-round shrink of the live pins assumed before two counts are known (the
 // measured ratio on the synthetic workloads lies between 0.2 and 0.35 in the
 // early rounds).
 constexpr double kPriorShrink = 0.3;
-// Batches: instances with at most this many pins are matched whole by one
-// workgroup (k_solo) unless the options say otherwise.
-constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
 // Rounds of per-round sums the solo part records (later rounds of a solo
 // instance count in the totals only).
 constexpr int kSoloRounds = 1 << 16;
-// One instance: the tail workgroup takes over a round with at most this many
-// live pins (and at most kTailCap live edges).  Off unless asked for: on the
-// synthetic workloads a round in one workgroup costs as much as a round of
-// the grid-wide kernels (both are a chain of dependent memory accesses).
-constexpr int kDefaultTailPins = -1;
+// The tail takes at most this many live edges.
 constexpr int kTailCap = 1 << 16;
 // Rows of the tail record copied with the round counters at each check.
 constexpr int kTailRowsFirst = 64;
 // Binned maximum (bin_shift > 0): a round uses it when the host expects at
 // least n / 2 surviving pins (below that the reduction's fixed cost, one
-// launch and a pass over every bin, outweighs the atomics it saves).  Off by
-// default: it won on hub-stress (uniform degrees, 1.29 -> 1.24 ms) and lost
-// on power-law (skewed degrees, whose filtered atomics are cheap: 1.05 ->
-// 1.11 ms); the autotuner tries it per shape.
+// launch and a pass over every bin, outweighs the atomics it saves).
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -1,0 +1,40 @@
+// Schedule defaults: the values an hgm_opts schedule field of 0 stands for.
+// Shared by the host driver (api.hip), which applies them, and the
+// autotuner (tune.cpp), which starts its search from them.  Any value gives
+// the same matching; these are the fastest measured on the MI355X.
+#pragma once
+
+#include <stdint.h>
+
+namespace hgm {
+
+constexpr int kDefaultHubThreshold = 8192;
+constexpr int kBlocksPerCu = 8;
+// Workgroups of the edge kernels (fixed, device independent, so that the
+// workspace size does not depend on the device).  Swept on the MI355X (256
+// CUs): one instance runs fastest at 1536 (power-law 1.030 -> 0.945 ms
+// against 2048, hub-stress 1.287 -> 1.253, graphs 3-4% faster), a batch's
+// round kernels at 4096 (18.3 -> 16.9 ms on 4,096 instances).
+constexpr int kEdgeGrid = 1536;
+constexpr int kEdgeGridBatch = 4096;
+// The test clears the whole next maximum buffer by streaming when a round has
+// at least n / kFullClearRatio live pins, else at each pin it visits.
+constexpr int kFullClearRatio = 8;
+constexpr int kHotDegree = 64;        // AUTO's round-0 form: degree of a hot vertex
+constexpr int kFirstBatchPct = 40;    // first batch of rounds: 0.40 log2(kappa)
+constexpr int kFirstBatchPctGraph = 35;
+// Batches: instances with at most this many pins are matched whole by one
+// workgroup (k_solo) unless the options say otherwise.
+constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
+// One instance: the tail workgroup takes over a round with at most this many
+// live pins (and at most 65536 live edges).  Off unless asked for: on the
+// synthetic workloads a round in one workgroup costs as much as a round of
+// the grid-wide kernels (both are a chain of dependent memory accesses).
+constexpr int kDefaultTailPins = -1;
+// Binned maximum (bin_shift > 0).  Off by default: it won on hub-stress
+// (uniform degrees, 1.29 -> 1.24 ms) and lost on power-law (skewed degrees,
+// whose filtered atomics are cheap: 1.05 -> 1.11 ms); the autotuner tries it
+// per shape.
+constexpr int kDefaultBinShift = -1;
+
+}  // namespace hgm

@@ -31,8 +31,11 @@
 #include <vector>
 
 #include "hgm.h"
+#include "schedule.h"
 
 namespace {
+
+using namespace hgm;
 
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -56,7 +59,7 @@ std::vector<Knob> knobs(bool batch) {
         {"clear", &hgm_opts::clear_ratio, {2, 8, 32}, 0},
         {"first", &hgm_opts::first_batch_pct, {25, 40, 55}, 0},
         {"tail", &hgm_opts::tail_pins, {-1, 1024, 4096, 32768}, 2},
-        {"bins", &hgm_opts::bin_shift, {0, 12, 13, 14}, 2},
+        {"bins", &hgm_opts::bin_shift, {-1, 12, 13, 14}, 2},
     };
     std::vector<Knob> out;
     for (auto &x : k)
@@ -77,26 +80,27 @@ hgm_opts largest_workspace(const hgm_opts *base) {
     o.hub_threshold = o.hub_threshold ? std::min(o.hub_threshold, kMinTunedHub) : kMinTunedHub;
     if (o.solo_max_kappa < 0) o.solo_max_kappa = 0;
     if (o.tail_pins <= 0) o.tail_pins = 32768;
-    if (o.bin_shift >= 0) o.bin_shift = 14;  // bins wherever any candidate shift allows them
+    o.bin_shift = 14;  // bins wherever any candidate shift allows them
     return o;
 }
 
 // The library default of each field, as the value the tuner reports.
-int32_t default_of(const char *name, bool graph) {
-    if (!strcmp(name, "solo")) return 1 << 20;
-    if (!strcmp(name, "grid")) return 2048;
-    if (!strcmp(name, "bpc")) return 8;
-    if (!strcmp(name, "hub")) return 8192;
-    if (!strcmp(name, "hot")) return 64;
-    if (!strcmp(name, "clear")) return 8;
-    if (!strcmp(name, "first")) return graph ? 35 : 40;
-    if (!strcmp(name, "tail")) return -1;
+int32_t default_of(const char *name, bool batch, bool graph) {
+    if (!strcmp(name, "solo")) return (int32_t)kDefaultSoloMaxKappa;
+    if (!strcmp(name, "grid")) return batch ? kEdgeGridBatch : kEdgeGrid;
+    if (!strcmp(name, "bpc")) return kBlocksPerCu;
+    if (!strcmp(name, "hub")) return kDefaultHubThreshold;
+    if (!strcmp(name, "hot")) return kHotDegree;
+    if (!strcmp(name, "clear")) return kFullClearRatio;
+    if (!strcmp(name, "first")) return graph ? kFirstBatchPctGraph : kFirstBatchPct;
+    if (!strcmp(name, "tail")) return kDefaultTailPins;
+    if (!strcmp(name, "bins")) return kDefaultBinShift;
     return 0;
 }
 
 void fill_defaults(hgm_opts *o, bool batch, bool graph) {
     for (auto &k : knobs(batch))
-        if (o->*(k.field) == 0) o->*(k.field) = default_of(k.name, graph);
+        if (o->*(k.field) == 0) o->*(k.field) = default_of(k.name, batch, graph);
 }
 
 // Shape bucket of a matching: device, kind, variant and layout, log2 of the
