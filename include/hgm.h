@@ -143,20 +143,25 @@ typedef struct hgm_opts {
                                 workgroup runs every remaining round
                                 (0 = library default: never; -1 = never) */
     int32_t bin_shift;       /* hgm_match, AUTO with the vertex side, offset
-                                layout: 10..14 = the next round's per-vertex
-                                maximum by propagation blocking instead of
-                                atomics, in rounds with at least n / 2
-                                surviving pins: the retire pass writes each
-                                surviving pin's (vertex, key) record to the
-                                bin of its 2^bin_shift-vertex range (hub pins
-                                excepted) and one workgroup per bin reduces
-                                it in LDS.  At most 1024 bins, else off.
-                                Needs 10 kappa bytes more workspace.  Pays
-                                where most pins lie on low-degree vertices.
-                                0 = library default (off); -1 = off.  The
-                                bins' capacities are v_off's degree sums, so
-                                a v_off that is not e_pins' transpose can
-                                overflow one: HGM_E_CSR. */
+                                layout: the next round's per-vertex maximum
+                                by propagation blocking instead of atomics,
+                                in rounds with at least n / 2 surviving pins:
+                                the retire pass writes each surviving pin's
+                                (vertex, key) record to the bin of its
+                                2^bin_shift-vertex range (hub pins excepted)
+                                and one workgroup per bin reduces it in LDS.
+                                It pays where most pins lie on low-degree
+                                vertices.  0 = library default (automatic:
+                                for n >= 2^17 and kappa >= 2^20, about 128
+                                bins, used when the degree profile sends
+                                round 0 to the vertex form, i.e. fewer than
+                                half the pins lie on vertices of hot_degree
+                                or more); 10..14 = that shift in every such
+                                round; -1 = off.  At most 1024 bins, else
+                                off.  Bins take 10 kappa bytes more
+                                workspace.  Their capacities are v_off's
+                                degree sums, so a v_off that is not e_pins'
+                                transpose can overflow one: HGM_E_CSR. */
 } hgm_opts;
 
 /* Kernel classes reported by the timing statistics. */

@@ -31,9 +31,15 @@ constexpr int kSoloRounds = 1 << 16;
 constexpr int kTailCap = 1 << 16;
 // Rows of the tail record copied with the round counters at each check.
 constexpr int kTailRowsFirst = 64;
-// Binned maximum (bin_shift > 0): a round uses it when the host expects at
-// least n / 2 surviving pins (below that the reduction's fixed cost, one
-// launch and a pass over every bin, outweighs the atomics it saves).
+// Binned maximum: a round uses it when the host expects at least n / 2
+// surviving pins (below that the reduction's fixed cost, one launch and a
+// pass over every bin, outweighs the atomics it saves).  bin_shift 0
+// (automatic): instances of at least these sizes, bins of 2^(ceil(log2 n) -
+// 7) vertices (about 128 bins) clamped to [2^12, 2^14], and on the device
+// only where the degree profile sent round 0 to the vertex form.
+constexpr int64_t kBinAutoMinN = (int64_t)1 << 17;
+constexpr int64_t kBinAutoMinKappa = (int64_t)1 << 20;
+constexpr int kBinAutoLo = 12, kBinAutoHi = 14;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -60,7 +66,7 @@ struct Opts {
     int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part)
     int edge_grid, blocks_per_cu, clear_ratio, hot_degree, first_batch_pct;  // 0 = per kind
     int64_t tail_pins;  // one instance: tail bound (-1: no tail)
-    int bin_shift;      // binned maximum: log2 vertices per bin, <= 0 off
+    int bin_shift;      // binned maximum: log2 vertices per bin, 0 automatic, -1 off
     bool reseed;            // priorities redrawn every round (round_seed)
     bool pairs;             // graph: two pins per edge at e_pins[2e], no offsets
     bool adaptive;          // rounds_per_sync chosen per batch from the decay of live pins
@@ -126,9 +132,15 @@ bool uses_live_key(const Opts &o) { return o.variant == HGM_VARIANT_CREW; }
 // of one instance: AUTO with the vertex side.
 int bin_shift_for(int64_t n, int64_t kappa, const Opts &o, bool batch) {
     if (batch || o.pairs || o.variant != HGM_VARIANT_AUTO || !o.have_vertex_side ||
-        o.bin_shift <= 0 || n <= 0 || kappa <= 0)
+        o.bin_shift < 0 || n <= 0 || kappa <= 0)
         return 0;
-    const int rb = o.bin_shift;
+    int rb = o.bin_shift;
+    if (rb == 0) {  // automatic: large instances, about 128 bins
+        if (n < kBinAutoMinN || kappa < kBinAutoMinKappa) return 0;
+        int lg = 0;
+        while (((int64_t)1 << lg) < n) ++lg;
+        rb = std::min(kBinAutoHi, std::max(kBinAutoLo, lg - 7));
+    }
     const int64_t nb = (n + ((int64_t)1 << rb) - 1) >> rb;
     return nb <= kBinMaxBins ? rb : 0;
 }
@@ -267,6 +279,7 @@ State carve(void *ws, const Layout &L, const Opts &o) {
     s.bin_cursor = L.bin_nb ? (uint32_t *)(b + L.bin_cursor) : nullptr;
     s.bin_rb = L.bin_rb;
     s.bin_nb = L.bin_nb;
+    s.bin_auto = o.bin_shift == 0;
     return s;
 }
 

@@ -166,6 +166,8 @@ struct State {
     uint64_t *bin_key;         // [kappa]
     uint32_t *bin_cursor;      // [bin_nb] records written, zero between passes
     int32_t bin_rb, bin_nb;
+    int32_t bin_auto;          // bins only where round 0 took the vertex form (the
+                               // degree profile in `hot`); 0: in every binned round
 };
 
 constexpr int kBinMaxBins = 1024;     // bins of one instance at most

@@ -828,13 +828,28 @@ __global__ void __launch_bounds__(kBlock) k_retire(Graph g, State s, int round, 
     retire_body<kPairs, kScatter, kB, false>(g, s, round, kseed, rekey, L, nullptr, nullptr);
 }
 
-// The binned form; dynamic LDS: bin counts, then run positions (2 bin_nb words).
+__device__ __forceinline__ bool max0_edge_form(const Graph &g, const State &s);
+
+// Whether the binned form runs: always with an explicit bin size; with the
+// automatic one only where round 0 took the vertex form, i.e. most pins lie
+// on vertices below the hot degree.  There a vertex sees few records per
+// round, so nearly every filtered read is followed by its atomic; on skewed
+// degrees the filter stops most of them and the atomic scatter is faster.
+__device__ __forceinline__ bool bins_run(const Graph &g, const State &s) {
+    return !s.bin_auto || !max0_edge_form(g, s);
+}
+
+// The binned form; dynamic LDS: bin counts, then run positions (2 bin_nb
+// words).  Where bins_run says no, the atomic scatter instead.
 __global__ void __launch_bounds__(kBlock) k_retire_bin(Graph g, State s, int round,
                                                        uint32_t kseed, int rekey) {
     __shared__ ChunkLds L;
     __shared__ HubTable H;
     extern __shared__ uint32_t bcnt[];
-    retire_body<false, true, false, true>(g, s, round, kseed, rekey, L, &H, bcnt);
+    if (bins_run(g, s))
+        retire_body<false, true, false, true>(g, s, round, kseed, rekey, L, &H, bcnt);
+    else
+        retire_body<false, true, false, false>(g, s, round, kseed, rekey, L, nullptr, nullptr);
 }
 
 // Reduces bin j (workgroup j): the maximum key of each of its vertices over
@@ -844,6 +859,7 @@ __global__ void __launch_bounds__(kBlock) k_retire_bin(Graph g, State s, int rou
 // the bin's cursor for the next round.
 __global__ void __launch_bounds__(kBinThreads) k_bin_max(Graph g, State s, int round) {
     extern __shared__ unsigned long long tile[];
+    if (!bins_run(g, s)) return;  // the retire pass scattered by atomics
     const int j = blockIdx.x;
     const int rb = s.bin_rb;
     const int64_t v0 = (int64_t)j << rb;

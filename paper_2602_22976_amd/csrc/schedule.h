@@ -31,10 +31,10 @@ constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
 // synthetic workloads a round in one workgroup costs as much as a round of
 // the grid-wide kernels (both are a chain of dependent memory accesses).
 constexpr int kDefaultTailPins = -1;
-// Binned maximum (bin_shift > 0).  Off by default: it won on hub-stress
-// (uniform degrees, 1.29 -> 1.24 ms) and lost on power-law (skewed degrees,
-// whose filtered atomics are cheap: 1.05 -> 1.11 ms); the autotuner tries it
-// per shape.
-constexpr int kDefaultBinShift = -1;
+// Binned maximum: automatic by default (0): on for large instances whose
+// round 0 takes the vertex form, where it won (hub-stress 1.26 -> 1.18 ms);
+// skewed degrees keep the atomic scatter, which won there (power-law 1.05
+// against 1.11 ms with bins).
+constexpr int kDefaultBinShift = 0;
 
 }  // namespace hgm

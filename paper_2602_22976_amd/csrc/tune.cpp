@@ -59,7 +59,7 @@ std::vector<Knob> knobs(bool batch) {
         {"clear", &hgm_opts::clear_ratio, {2, 8, 32}, 0},
         {"first", &hgm_opts::first_batch_pct, {25, 40, 55}, 0},
         {"tail", &hgm_opts::tail_pins, {-1, 1024, 4096, 32768}, 2},
-        {"bins", &hgm_opts::bin_shift, {-1, 12, 13, 14}, 2},
+        {"bins", &hgm_opts::bin_shift, {-1, 0, 12, 13, 14}, 2},
     };
     std::vector<Knob> out;
     for (auto &x : k)

@@ -83,26 +83,29 @@ def test_workspace_size_layout(lib):
 
 def test_workspace_bins(lib):
     """The binned maximum's records (2-byte index and 8-byte key per pin) and
-    cursors are carved only where bins run: an explicit shift, AUTO with the
-    vertex side, offset layout, at most 1024 bins."""
+    cursors are carved only where bins can run: AUTO with the vertex side,
+    offset layout, at most 1024 bins; automatically (the default) for n >=
+    2^17 and kappa >= 2^20."""
     big = _csr(2_000_000, 5_000_000, 30_000_000)
     off = hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=-1))
-    assert hgm.hgm_workspace_size(big) == off  # off by default
-    on = hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=12))
-    assert 10 * 30_000_000 <= on - off <= 10 * 30_000_000 + 3 * 4096 + 1024
-    for rb in (13, 14):  # same size for every shift that fits
-        assert hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=rb)) == on
+    auto = hgm.hgm_workspace_size(big)
+    assert 10 * 30_000_000 <= auto - off <= 10 * 30_000_000 + 3 * 4096 + 1024
+    for rb in (12, 13, 14):  # same size for every shift that fits
+        assert hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=rb)) == auto
     # 2^21 vertices in bins of 2^10 would be 1954 bins: no bins
     assert hgm.hgm_workspace_size(big, hgm.make_opts(bin_shift=10)) == off
     # CRCW, CREW, graphs and instances without the vertex side have no bins
     for variant in ("crcw", "crew"):
         assert hgm.hgm_workspace_size(big, hgm.make_opts(variant, bin_shift=12)) == \
-            hgm.hgm_workspace_size(big, hgm.make_opts(variant))
+            hgm.hgm_workspace_size(big, hgm.make_opts(variant, bin_shift=-1))
     edge_only = _csr(2_000_000, 5_000_000, 30_000_000)
     edge_only.v_off = edge_only.v_edges = None
     assert hgm.hgm_workspace_size(edge_only, hgm.make_opts(bin_shift=12)) == \
-        hgm.hgm_workspace_size(edge_only)
+        hgm.hgm_workspace_size(edge_only, hgm.make_opts(bin_shift=-1))
+    # small instances: automatic leaves bins off, an explicit shift turns them on
     small = _csr(1000, 2000, 8000)
+    assert hgm.hgm_workspace_size(small) == hgm.hgm_workspace_size(
+        small, hgm.make_opts(bin_shift=-1))
     assert hgm.hgm_workspace_size(small, hgm.make_opts(bin_shift=10)) >= \
         hgm.hgm_workspace_size(small) + 10 * 8000
     for bad in (1, 9, 15, -2):
