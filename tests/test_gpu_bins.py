@@ -121,3 +121,24 @@ def test_bins_overflow_is_an_error(hgm):
     torch.cuda.synchronize()
     print("same workspace, real instance", flush=True)
     _check(hgm, g, 4, ws=ws, bin_shift=10)
+
+
+@pytest.mark.parametrize("tail", [1000, 1 << 30])
+def test_bins_with_tail(hgm, tail):
+    """Binned early rounds, then the one-workgroup tail: from round 1 on
+    (bound 2^30) or for the last rounds (bound 1000)."""
+    g = synth.config_power_law(seed=617, n=50_000, m=150_000)
+    print(f"bins with tail {tail}", flush=True)
+    st = _check(hgm, g, 6, bin_shift=11, hub_threshold=256, tail_pins=tail)
+    assert st["rounds"] > 0
+
+
+def test_bins_automatic_follows_degree_profile(hgm):
+    """The automatic setting (the default) allocates bins for instances with
+    n >= 2^17 and kappa >= 2^20 and uses them only where round 0 takes the
+    vertex form; both cases equal the oracle."""
+    for g in (synth.config_hub_stress(seed=618, n=150_000, m=300_000),
+              synth.config_power_law(seed=619, n=150_000, m=400_000)):
+        assert g.n >= 1 << 17 and g.kappa >= 1 << 20
+        print(f"automatic bins n={g.n} kappa={g.kappa}", flush=True)
+        _check(hgm, g, 8)
