@@ -74,6 +74,43 @@ __device__ __forceinline__ int wave_inclusive_sum(int v) {
     return v;
 }
 
+// Segmented inclusive max-scan over a wave with DPP lane moves (VALU), not
+// ds_bpermute shuffles, which go through the LDS pipe that the vertex pass
+// already keeps busy with its item searches.  Segments are runs of equal j
+// (contiguous).  Row shifts by 1, 2, 4, 8 scan each row of 16 lanes; then
+// lane 15 of each row is broadcast into rows 1 and 3, and lane 31 into rows
+// 2 and 3.  A lane takes the value it reads only when it reads from its own
+// segment; lanes with no source keep j = -2, which equals no j.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_max_dpp(uint64_t &k, int j) {
+    const int yj = __builtin_amdgcn_update_dpp(-2, j, kCtrl, kRowMask, 0xF, false);
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)k, kCtrl, kRowMask, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k >> 32), kCtrl,
+                                                              kRowMask, 0xF, false);
+    const uint64_t y = ((uint64_t)hi << 32) | lo;
+    if (yj == j && y > k) k = y;
+}
+
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
+              kDppRowShr8 = 0x118, kDppBcast15 = 0x142, kDppBcast31 = 0x143,
+              kDppWaveShl1 = 0x130;
+
+__device__ __forceinline__ uint64_t wave_segmented_max(uint64_t k, int j) {
+    seg_max_dpp<kDppRowShr1, 0xF>(k, j);
+    seg_max_dpp<kDppRowShr2, 0xF>(k, j);
+    seg_max_dpp<kDppRowShr4, 0xF>(k, j);
+    seg_max_dpp<kDppRowShr8, 0xF>(k, j);
+    seg_max_dpp<kDppBcast15, 0xA>(k, j);
+    seg_max_dpp<kDppBcast31, 0xC>(k, j);
+    return k;
+}
+
+// j of the next lane (lane 63: -2).
+__device__ __forceinline__ int next_lane_j(int j) {
+    return __builtin_amdgcn_update_dpp(-2, j, kDppWaveShl1, 0xF, 0xF, false);
+}
+
 // Exclusive block-wide prefix sum of v; *total receives the block sum.
 // Contains two barriers; every thread of the block must call it.
 __device__ __forceinline__ int block_exclusive_sum(int v, int *wave_tmp, int *total) {
@@ -1059,14 +1096,8 @@ __device__ __forceinline__ void vertex_max_body(const Graph &g, const State &s, 
                 }
             }
             // segmented inclusive max-scan over the wave, segments = equal j
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                uint64_t y = __shfl_up(k, o, kWave);
-                int yj = __shfl_up(j, o, kWave);
-                if (lane >= o && yj == j && y > k) k = y;
-            }
-            int nj = __shfl_down(j, 1, kWave);
-            bool last = (lane == kWave - 1) || (nj != j);
+            k = wave_segmented_max(k, j);
+            const bool last = next_lane_j(j) != j;  // lane 63 reads -2
             if (j >= 0 && last && k) atomicMax((unsigned long long *)&L.key[j], (unsigned long long)k);
         }
         __syncthreads();
