@@ -734,6 +734,30 @@ def _pmc_by_class(root, counter):
     return kib, n
 
 
+def summarize_counters(root):
+    """Markdown table of a rocprofv3 --pmc run (csv) with any counters: per
+    kernel of the library, its dispatches and each counter summed over them."""
+    rows = _csv_rows(root, "counter_collection.csv")
+    per, disp, names = {}, {}, set()
+    for r in rows:
+        if kernel_class(r["Kernel_Name"]) is None:
+            continue
+        k = kernel_short_name(r["Kernel_Name"])
+        c = r["Counter_Name"]
+        names.add(c)
+        per.setdefault(k, {}).setdefault(c, 0.0)
+        per[k][c] += float(r["Counter_Value"])
+        disp.setdefault(k, set()).add(r.get("Dispatch_Id", ""))
+    cols = sorted(names)
+    out = ["| kernel | dispatches | " + " | ".join(cols) + " |",
+           "|---|---|" + "---|" * len(cols)]
+    order = sorted(per, key=lambda k: -max(per[k].values()))
+    for k in order:
+        out.append(f"| {k} | {len(disp[k])} | " +
+                   " | ".join(f"{per[k].get(c, 0.0):.3g}" for c in cols) + " |")
+    return "\n".join(out)
+
+
 def summarize_pmc(workload, fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, calls,
                   copy_mib=1024):
     """JSON line of calibrated HBM traffic per kernel class and per hgm call:
@@ -891,6 +915,9 @@ def main():
                     help="MiB: only run a plain device copy (PMC calibration) and exit")
     ap.add_argument("--summarize-trace", default=None,
                     help="rocprofv3 --kernel-trace output directory (csv): print its table")
+    ap.add_argument("--summarize-counters", default=None,
+                    help="rocprofv3 --pmc output directory (csv, any counters): print the "
+                         "per-kernel sums")
     ap.add_argument("--summarize-pmc", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
                     help="rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of the "
@@ -905,6 +932,9 @@ def main():
 
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
+        return
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters))
         return
     if args.summarize_pmc:
         print(summarize_pmc(args.workload, *args.summarize_pmc, calls=max(1, args.calls)))

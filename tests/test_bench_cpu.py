@@ -75,3 +75,23 @@ def test_byte_model_tail():
     r1 = (20 * 4 + 12 * 12 + 4 * 1 + 3) + (20 * 4 + 5 * 12 + 20 * 2 + 16 * 6)
     r2 = (20 * 2 + 12 * 6 + 4 * 2 + 6) + (20 * 2 + 5 * 6)
     assert out["tail"] == 40 * 4 + r1 + r2
+
+
+def test_summarize_counters(tmp_path):
+    """The per-kernel counter table of a rocprofv3 --pmc csv: sums per
+    library kernel over its dispatches, other kernels left out."""
+    import bench
+    d = tmp_path / "run" / "host"
+    d.mkdir(parents=True)
+    rows = [("1", "void hgm::(anonymous namespace)::k_test<false, 1, false>(hgm::Graph)", "SQ_WAVES", "10"),
+            ("1", "void hgm::(anonymous namespace)::k_test<false, 1, false>(hgm::Graph)", "SQ_WAIT_ANY", "7"),
+            ("2", "void hgm::(anonymous namespace)::k_test<false, 1, false>(hgm::Graph)", "SQ_WAVES", "5"),
+            ("3", "some_other_kernel(int)", "SQ_WAVES", "99")]
+    with open(d / "run_counter_collection.csv", "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for r in rows:
+            f.write(",".join(f'"{x}"' for x in r) + "\n")
+    out = bench.summarize_counters(str(tmp_path)).splitlines()
+    assert out[0] == "| kernel | dispatches | SQ_WAIT_ANY | SQ_WAVES |"
+    assert out[2] == "| k_test<false, 1, false> | 2 | 7 | 15 |"
+    assert len(out) == 3
