@@ -64,13 +64,23 @@ __device__ __forceinline__ uint64_t round_key(const Graph &g, const State &s, ui
     return edge_key<false>(g, s, kseed, e);
 }
 
+// v plus the value DPP control kCtrl reads for this lane (0 where it reads
+// none or the row is masked off).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_add(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, kCtrl, kRowMask, 0xF, false);
+}
+
+// Inclusive prefix sum over a wave with DPP lane moves (VALU, no LDS
+// traffic): row shifts by 1, 2, 4, 8 sum each row of 16 lanes; lane 15 of
+// each row then adds into rows 1 and 3, and lane 31 into rows 2 and 3.
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        int y = __shfl_up(v, o, kWave);
-        if (lane >= o) v += y;
-    }
+    v = dpp_add<0x111, 0xF>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xF>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xF>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xF>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31
     return v;
 }
 
