@@ -118,7 +118,8 @@ typedef struct hgm_opts {
                                 round inside it, with their per-vertex state
                                 in LDS; the others go through the round
                                 kernels together.  0 = library default
-                                (2^20), -1 = none. */
+                                (the batch's kappa_total / 1024, clamped to
+                                [2^12, 2^20]), -1 = none. */
     /* Schedule (any value gives the same result; hgm_tune picks them per
      * shape).  0 = library default for each. */
     int32_t edge_grid;       /* workgroups of the edge-centric kernels, each

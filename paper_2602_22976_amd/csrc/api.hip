@@ -63,7 +63,7 @@ void edge_schedule(int64_t m, int edge_grid, int *grid, int *region) {
 
 struct Opts {
     int variant, hub_threshold, rounds_per_sync, validate, max_rounds;
-    int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part)
+    int64_t solo_max_kappa;  // batches: solo part bound (-1: no solo part, 0: by size)
     int edge_grid, blocks_per_cu, clear_ratio, hot_degree, first_batch_pct;  // 0 = per kind
     int64_t tail_pins;  // one instance: tail bound (-1: no tail)
     int bin_shift;      // binned maximum: log2 vertices per bin, 0 automatic, -1 off
@@ -94,7 +94,7 @@ int resolve_opts(const hgm_opts *in, Opts *o) {
     o->reseed = d.reseed != 0;
     o->pairs = d.pairs != 0;
     if (d.solo_max_kappa < -1) return HGM_E_ARG;
-    o->solo_max_kappa = d.solo_max_kappa == 0 ? kDefaultSoloMaxKappa : d.solo_max_kappa;
+    o->solo_max_kappa = d.solo_max_kappa;  // 0: solo_auto_bound of the batch's pins
     if (d.edge_grid < 0 || d.edge_grid > 65536 || d.blocks_per_cu < 0 || d.blocks_per_cu > 32 ||
         d.clear_ratio < 0 || d.clear_ratio > (1 << 20) || d.hot_degree < 0 ||
         d.first_batch_pct < 0 || d.first_batch_pct > 400)
@@ -979,7 +979,7 @@ int hgm_match_batch(const hgm_batch *b, uint32_t *matched_bits, void *workspace,
         sa.e_base = b->e_base;
         sa.pin_base = b->pin_base;
         sa.word_base = b->word_base;
-        sa.max_kappa = o.solo_max_kappa;
+        sa.max_kappa = o.solo_max_kappa ? o.solo_max_kappa : solo_auto_bound(b->kappa_total);
         sa.lds_bytes = solo_lds_bytes();
         if (sa.lds_bytes <= 0) return HGM_E_HIP;
         sa.one_tile = solo_verts_for(sa.lds_bytes, 1);

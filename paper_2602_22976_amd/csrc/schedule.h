@@ -24,8 +24,20 @@ constexpr int kHotDegree = 64;        // AUTO's round-0 form: degree of a hot ve
 constexpr int kFirstBatchPct = 40;    // first batch of rounds: 0.40 log2(kappa)
 constexpr int kFirstBatchPctGraph = 35;
 // Batches: instances with at most this many pins are matched whole by one
-// workgroup (k_solo) unless the options say otherwise.
-constexpr int64_t kDefaultSoloMaxKappa = (int64_t)1 << 20;
+// workgroup each (k_solo) unless the options say otherwise: the batch's
+// total pins / kSoloAutoDivisor, clamped to [kSoloAutoMin, kSoloAutoMax].
+// One compute unit matches a solo instance at about 1.2e8 pins/s, the round
+// kernels the whole batch at about 3e10, so this keeps the longest solo
+// instance within about a quarter of the round kernels' time for the batch.
+// Measured: 4,096 instances (4.8e8 pins) 16.35 -> 15.85 ms against the
+// former fixed 2^20; 1,024 instances (1.2e8 pins) 8.4 -> about 5 ms.
+constexpr int64_t kSoloAutoDivisor = 1024;
+constexpr int64_t kSoloAutoMin = (int64_t)1 << 12;
+constexpr int64_t kSoloAutoMax = (int64_t)1 << 20;
+inline int64_t solo_auto_bound(int64_t kappa_total) {
+    const int64_t b = kappa_total / kSoloAutoDivisor;
+    return b < kSoloAutoMin ? kSoloAutoMin : b > kSoloAutoMax ? kSoloAutoMax : b;
+}
 // One instance: the tail workgroup takes over a round with at most this many
 // live pins (and at most 65536 live edges).  Off unless asked for: on the
 // synthetic workloads a round in one workgroup costs as much as a round of

@@ -201,7 +201,7 @@ int request_content(const hgm_request &q, bool vside) {
 // and bitmap bits are 32-bit.
 constexpr int64_t kWaveLimit = ((int64_t)1 << 31) - 1;
 // Default solo bound of a wave (measured on the served workload: 2^17 and
-// below served 16% more requests per second than the batch default 2^20,
+// below served 16% more requests per second than a bound of 2^20,
 // with half the p99 latency).
 constexpr int32_t kWaveSoloMaxKappa = 1 << 17;
 

@@ -86,7 +86,7 @@ hgm_opts largest_workspace(const hgm_opts *base) {
 
 // The library default of each field, as the value the tuner reports.
 int32_t default_of(const char *name, bool batch, bool graph) {
-    if (!strcmp(name, "solo")) return (int32_t)kDefaultSoloMaxKappa;
+    if (!strcmp(name, "solo")) return 0;  // by the batch's size (solo_auto_bound)
     if (!strcmp(name, "grid")) return batch ? kEdgeGridBatch : kEdgeGrid;
     if (!strcmp(name, "bpc")) return kBlocksPerCu;
     if (!strcmp(name, "hub")) return kDefaultHubThreshold;

@@ -230,13 +230,19 @@ def test_batch_round_limit(hgm, solo):
 
 def test_solo_part_is_used(hgm):
     """Timing statistics show the solo kernel once per call when instances
-    fit its bound, and the round kernels alone when it is off."""
+    fit its bound, and the round kernels alone when it is off.  The default
+    bound follows the batch's total pins (here the 2^12 floor): the small
+    instances go to the solo part, the larger ones to the round kernels."""
     import torch
     b = synth.config_batched(seed=78, count=64, n_lo=20, n_hi=2000)
     db = hgm.DeviceBatch.from_host(b, "cuda:0")
-    _, st = hgm.match_batch(db, hgm.make_opts("auto"), timing=True)
+    _, st = hgm.match_batch(db, hgm.make_opts("auto", solo_max_kappa=1 << 20), timing=True)
     assert st["kernel_launches"]["solo"] == 1 and st["kernel_ms"]["solo"] > 0
     assert st["kernel_launches"]["test"] == 0     # every instance ran in the solo part
+    kap = np.diff(b.pin_base)
+    assert kap.sum() // 1024 < 4096 and (kap <= 4096).any() and (kap > 4096).any()
+    _, st = hgm.match_batch(db, hgm.make_opts("auto"), timing=True)
+    assert st["kernel_launches"]["solo"] == 1 and st["kernel_launches"]["test"] > 0
     _, st = hgm.match_batch(db, hgm.make_opts("auto", solo_max_kappa=-1), timing=True)
     assert st["kernel_launches"]["solo"] == 0 and st["kernel_launches"]["test"] > 0
     torch.cuda.synchronize()
